@@ -1,0 +1,194 @@
+/*
+ * mri_admm.h -- C ABI of libmriadmm, an MI355X (gfx950) implementation of
+ * compressed-sensing ADMM reconstruction of multi-coil non-Cartesian MRI with
+ * the non-uniform DFT written as dense complex matrix products
+ * (Lu et al., "Accelerating MRI Reconstruction on TPUs", arXiv:2006.14080).
+ *
+ * Notation follows the paper: image rho (here x), coil sensitivities s,
+ * trajectory k, k-space data d (here y), regularisation lambda, augmented
+ * Lagrangian penalty beta (eq. (5)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  All arrays are dense, C-contiguous, little-endian:
+ *   image   [B][ny][nx]          mri_c32, x (column) fastest
+ *   smaps   [B or 1][nc][ny][nx] mri_c32
+ *   traj    [B or 1][nk][2]      double, radians per pixel; column 0 pairs
+ *                                with x, column 1 with y
+ *   data    [B][nc][nk]          mri_c32, coil-major
+ *   grad    [B][2][ny][nx]       mri_c32, [0] = x-difference, [1] = y-difference
+ * Pixel (i, j) sits at the centred integer offsets y = i - ny/2, x = j - nx/2
+ * (integer division), so the Cartesian case equals the centred FFT.
+ *
+ * Ownership.  Every array argument is a caller-owned DEVICE pointer, 8-byte
+ * aligned; the library never retains one after the call returns.  The caller
+ * allocates the workspace (size from mri_workspace_bytes); the library never
+ * allocates device memory on these paths.
+ *
+ * Streams.  `stream` is a hipStream_t (NULL = default stream).  Every call
+ * only enqueues work on it and returns; outputs are valid once the stream
+ * reaches that point.  Calls are thread-safe when each thread uses its own
+ * stream and its own workspace.
+ *
+ * Errors.  Entry points return 0 (MRI_OK) or a negative MRI_E* code and
+ * enqueue nothing on error.  Outputs are unspecified after an error.
+ * No C++ exception crosses this interface.
+ */
+#ifndef MRI_ADMM_H
+#define MRI_ADMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* complex64, the layout of torch.complex64 / std::complex<float>. */
+typedef struct { float re, im; } mri_c32;
+
+/* Problem shape.  batch >= 1 independent slices of one shape.
+ * traj_batched / smaps_batched = 0: one array shared by every slice;
+ * = 1: one array per slice.  nx != ny is allowed. */
+typedef struct {
+    int32_t nx, ny, ncoils;
+    int64_t nk;
+    int32_t batch;
+    int32_t traj_batched, smaps_batched;
+} mri_shape;
+
+/* Arithmetic of the NUDFT matrix products. */
+enum {
+    MRI_FP32 = 0,   /* FP32 MFMA products, FP32 accumulation */
+    MRI_BF16X3 = 1  /* split-BF16 compensated products (hi*hi + hi*lo + lo*hi)
+                       on BF16 MFMA, FP32 accumulation (Sec. II-A) */
+};
+
+enum {
+    MRI_OK = 0,
+    MRI_EINVAL = -1,    /* NULL pointer, bad shape or parameter */
+    MRI_ENOMEM = -2,    /* workspace too small / budget exceeded */
+    MRI_EHIP = -3,      /* HIP runtime error (see mri_strerror / mri_last_hip_error) */
+    MRI_ENOTSUP = -4,   /* unsupported precision or shape */
+    MRI_ENUMERIC = -5   /* non-finite value met during a solve (reported in stats) */
+};
+
+/* Operation selector for mri_workspace_bytes. */
+enum { MRI_OP_FORWARD = 0, MRI_OP_ADJOINT = 1, MRI_OP_ADMM = 2 };
+
+/* Largest supported sizes (one GPU's share). */
+#define MRI_MAX_DIM 2048      /* nx, ny */
+#define MRI_MAX_COILS 64
+#define MRI_MAX_BATCH 4096
+
+/*
+ * nudft_forward -- y = F(x), eq. (1)-(2):
+ *   y[b][g][k] = sum_{i,j} s[g][i][j] x[b][i][j] exp(-i (w0_k x_j + w1_k y_i)).
+ * The phase matrix is never stored: it is generated tile by tile from the
+ * trajectory (argument reduced in FP64, Alg. 1), and the product is the
+ * separable form of Alg. 1, T = E_x (s (.) x)^T followed by a row sum
+ * against E_y.
+ *   x [B][ny][nx], smaps, traj as above, y [B][nc][nk] (written).
+ *   precision: MRI_FP32 or MRI_BF16X3.
+ *   ws/ws_bytes: workspace of at least mri_workspace_bytes(shape,
+ *   MRI_OP_FORWARD, NULL) bytes (may be NULL when that is 0).
+ * Errors: MRI_EINVAL, MRI_ENOTSUP, MRI_ENOMEM, MRI_EHIP.
+ */
+int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps,
+                  const double* traj, mri_c32* y, int precision,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * nudft_adjoint -- x = F^H(y): the adjoint of eq. (1) with the conjugate coil
+ * combine, which is the "inverse DFT" of Alg. 3 and the F^H of eq. (12)-(13):
+ *   x[b][i][j] = sum_g conj(s[g][i][j]) sum_k exp(+i (w0_k x_j + w1_k y_i)) y[b][g][k].
+ * No density compensation.  The sample sum is split over workgroups and the
+ * partial images are added in a fixed order, so results are bitwise
+ * reproducible run to run.
+ *   y [B][nc][nk], x [B][ny][nx] (written).  Workspace: MRI_OP_ADJOINT.
+ * Errors: as nudft_forward.
+ */
+int nudft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps,
+                  const double* traj, mri_c32* x, int precision,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * tv_forward -- g = Theta(x), the finite-difference sparsifying transform
+ * (Sec. III-A, Sec. IV-B): forward differences with periodic wrap,
+ *   g[b][0][i][j] = x[b][i][(j+1) mod nx] - x[b][i][j]
+ *   g[b][1][i][j] = x[b][(i+1) mod ny][j] - x[b][i][j].
+ *   x [B][ny][nx], g [B][2][ny][nx] (written).  Only nx, ny, batch are read.
+ * Errors: MRI_EINVAL, MRI_EHIP.
+ */
+int tv_forward(const mri_shape* shape, const mri_c32* x, mri_c32* g, void* stream);
+
+/*
+ * tv_adjoint -- x = Theta^H(g), the exact conjugate transpose of tv_forward:
+ *   x[i][j] = g0[i][(j-1) mod nx] - g0[i][j] + g1[(i-1) mod ny][j] - g1[i][j].
+ * Errors: MRI_EINVAL, MRI_EHIP.
+ */
+int tv_adjoint(const mri_shape* shape, const mri_c32* g, mri_c32* x, void* stream);
+
+/* ADMM parameters (Table I names).  beta is the paper's augmented-Lagrangian
+ * penalty (eq. (5)); the soft threshold of eq. (9) is lambda/beta and the
+ * normal matrix of eq. (12) carries beta/2.  rtol = atol = 0 runs exactly
+ * admm_iters x cg_iters steps (a step still stops early when its residual is
+ * exactly zero or CG breaks down).  cg_warm_start = 1 starts each CG solve
+ * from the current image, 0 from the initial image. */
+typedef struct {
+    double lambda, beta;
+    int32_t admm_iters, cg_iters;
+    double rtol, atol;
+    int32_t precision, cg_warm_start;
+} mri_admm_params;
+
+/* Per-slice solve report, written to device memory at the end of admm_solve. */
+typedef struct {
+    int32_t admm_iters_run;  /* ADMM iterations executed */
+    int32_t cg_steps_run;    /* CG steps executed, summed over ADMM iterations */
+    double alpha;            /* last ||rho' - rho||^2 / ||rho||^2 (Alg. 4) */
+    double tau;              /* last CG residual r^H r (Alg. 2) */
+    int32_t status;          /* MRI_OK or MRI_ENUMERIC */
+    int32_t pad;
+} mri_admm_stats;
+
+/*
+ * admm_solve -- the whole of Alg. 4 (ADMM, eq. (6)-(13)) with the rho-update
+ * solved by conjugate gradient (Alg. 2), per slice:
+ *   F^H y once; rho = x0 (or 0), eta = 0; then per iteration
+ *   mu = S_{lambda/beta}(Theta rho + eta)                  eq. (9)-(10)
+ *   b = F^H y + (beta/2) Theta^H (mu - eta)                 eq. (13)
+ *   solve (F^H F + (beta/2) Theta^H Theta) rho' = b by CG   eq. (11)-(12)
+ *   eta += Theta rho' - mu;  alpha = ||rho' - rho||^2/||rho||^2   eq. (8)
+ * stopping when the iteration cap is reached or alpha <= rtol^2.  CG starts
+ * from r = b - A rho, stops after cg_iters steps, when r^H r <= atol^2, or
+ * when d^H A d <= 0.  Vector arithmetic is FP32; dot products, norms and the
+ * CG/ADMM scalars are FP64.  The complex soft threshold shrinks magnitudes.
+ *   smaps, traj, y: inputs as above; x0 [B][ny][nx] or NULL (zeros);
+ *   x_out [B][ny][nx] (written); stats_dev: device array of B mri_admm_stats
+ *   or NULL.  Workspace: mri_workspace_bytes(shape, MRI_OP_ADMM, params).
+ * Nothing is copied back to the host and the host never waits: all control
+ * decisions (tolerances, breakdown) are taken on the device.
+ * Errors: MRI_EINVAL (lambda < 0, beta <= 0, negative counts, bad shape),
+ * MRI_ENOTSUP, MRI_ENOMEM, MRI_EHIP.
+ */
+int admm_solve(const mri_shape* shape, const mri_c32* smaps, const double* traj,
+               const mri_c32* y, const mri_c32* x0, const mri_admm_params* params,
+               mri_c32* x_out, mri_admm_stats* stats_dev,
+               void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes needed by an operation (params may be NULL except for
+ * MRI_OP_ADMM).  Returns 0 for an invalid shape. */
+size_t mri_workspace_bytes(const mri_shape* shape, int op, const mri_admm_params* params);
+
+/* Static description of an error code. */
+const char* mri_strerror(int code);
+
+/* Text of the last HIP error seen by this thread ("" if none). */
+const char* mri_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MRI_ADMM_H */

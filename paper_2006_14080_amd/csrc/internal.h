@@ -1,0 +1,63 @@
+// Internal interfaces of libmriadmm shared between the kernel files and the
+// host runtime.  Nothing here crosses the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/mri_admm.h"
+
+namespace mri {
+
+constexpr int kMaxItems = 16;     // problems per grouped launch
+
+// ---------------------------------------------------------------------------
+// NUDFT launch tables.  One "item" is a problem of one shape with nb slices;
+// a grouped launch covers up to kMaxItems items, each owning a contiguous
+// range of tiles.  Tables travel by value as kernel arguments, so a launch
+// needs no host-to-device copy and a captured graph keeps them.
+// ---------------------------------------------------------------------------
+struct NudftItem {
+    int32_t nx, ny, nc, nb;
+    int64_t nk;
+    const double* traj;  int64_t traj_bs;    // doubles per slice, 0 = shared
+    const float2* smaps; int64_t smaps_bs;   // complex per slice, 0 = shared
+    const float2* img;                       // [nb][ny][nx]   forward input
+    float2* data;                            // [nb][nc][nk]   forward output / adjoint input
+    float2* part;                            // [ksplit][nb][ny][nx] adjoint partial images
+    const int32_t* active;                   // per-slice run flag (nullable): slice b runs iff
+                                             // active[b * active_stride] != 0
+    int32_t active_stride;
+    int32_t ksplit;                          // adjoint: sample-range splits
+    int32_t kper;                            // adjoint: samples per split (multiple of 8)
+    int32_t tile_begin;                      // first tile of this item
+    int32_t ntiles;
+};
+
+struct NudftTable {
+    int32_t nitems;
+    int32_t total_tiles;
+    NudftItem it[kMaxItems];
+};
+
+// Forward tiling: 64 samples per workgroup, rows = all y in chunks of 256.
+constexpr int kFwdCols = 64;
+// Adjoint tiling: 64 x columns, 32 y rows, all coils (in groups of 8) per tile.
+constexpr int kAdjCols = 64;
+constexpr int kAdjRows = 32;
+constexpr int kAdjCoilGroup = 8;
+constexpr int kKStep = 8;          // complex K values per pipeline stage
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb);
+int64_t adj_tiles_per_split(int nx, int ny, int nb);
+// Choose the sample-range split of the adjoint for one problem.
+void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
+               int32_t* ksplit, int32_t* kper);
+
+hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s);
+hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s);
+
+}  // namespace mri

@@ -1,0 +1,449 @@
+// Vector kernels of the ADMM-TV solve (eq. (6)-(13), Alg. 2, Alg. 4): the
+// finite-difference transform and its adjoint, soft thresholding, the
+// right-hand side, the CG updates, the dual update, and the reduction that
+// finishes each application of the normal matrix A = F^H F + (beta/2) Theta^H Theta.
+//
+// All are memory-bound, one pixel per thread, coalesced along x.  Vector
+// arithmetic is FP32; inner products and norms accumulate in FP64 and are
+// summed in a fixed order: wave shuffles, waves in index order, then the
+// per-block partials in block order by the last block to arrive (an integer
+// arrival counter; no floating-point atomics), so results are reproducible.
+#include "device.h"
+#include "solver.h"
+
+namespace mri {
+namespace {
+
+struct Loc {
+    int item, b, blk;
+    int64_t pix;
+    bool valid;
+};
+
+__device__ __forceinline__ Loc locate(const SolveTable& t) {
+    const int g = blockIdx.x;
+    int i = 0;
+    while (i + 1 < t.nitems && g >= t.it[i + 1].block_begin) ++i;
+    const SolveItem& it = t.it[i];
+    const int local = g - it.block_begin;
+    Loc l;
+    l.item = i;
+    l.b = local / it.nblk;
+    l.blk = local % it.nblk;
+    l.pix = (int64_t)l.blk * kVecThreads + threadIdx.x;
+    l.valid = l.pix < it.npix;
+    return l;
+}
+
+// Periodic neighbours of pixel p in an ny x nx image.
+struct Nb {
+    int64_t xp, xm, yp, ym;   // (i, j+1), (i, j-1), (i+1, j), (i-1, j)
+};
+__device__ __forceinline__ Nb neighbours(int64_t p, int nx, int ny) {
+    const int i = (int)(p / nx), j = (int)(p - (int64_t)i * nx);
+    const int jp = j + 1 == nx ? 0 : j + 1, jm = j == 0 ? nx - 1 : j - 1;
+    const int ip = i + 1 == ny ? 0 : i + 1, im = i == 0 ? ny - 1 : i - 1;
+    Nb n;
+    n.xp = (int64_t)i * nx + jp;
+    n.xm = (int64_t)i * nx + jm;
+    n.yp = (int64_t)ip * nx + j;
+    n.ym = (int64_t)im * nx + j;
+    return n;
+}
+
+__device__ __forceinline__ double cnorm2(float2 a) {
+    return (double)a.x * a.x + (double)a.y * a.y;
+}
+
+// Block partials (two FP64 values) -> per-slice partial array; the last block
+// of the slice to arrive sums all partials in block order and calls fin().
+template <class Fin>
+__device__ __forceinline__ void reduce2_finalize(double v0, double v1, const SolveItem& it, int b, int blk, Fin fin) {
+    __shared__ double sm[2][kVecThreads / 64];
+    __shared__ double tot[2][kVecThreads / 64];
+    __shared__ int is_last;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    v0 = wave_sum(v0);
+    v1 = wave_sum(v1);
+    if (lane == 0) {
+        sm[0][w] = v0;
+        sm[1][w] = v1;
+    }
+    __syncthreads();
+    double* red = it.red + (int64_t)b * 2 * it.nblk;
+    if (tid == 0) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kVecThreads / 64; ++k) {
+            s0 += sm[0][k];
+            s1 += sm[1][k];
+        }
+        red[blk] = s0;
+        red[it.nblk + blk] = s1;
+        __threadfence();
+        const uint32_t old = __hip_atomic_fetch_add(&it.sc[b].counter, 1u, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+        is_last = (old == (uint32_t)(it.nblk - 1));
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = tid; k < it.nblk; k += kVecThreads) {
+        a0 += __builtin_nontemporal_load(&red[k]);
+        a1 += __builtin_nontemporal_load(&red[it.nblk + k]);
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if (lane == 0) {
+        tot[0][w] = a0;
+        tot[1][w] = a1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kVecThreads / 64; ++k) {
+            t0 += tot[0][k];
+            t1 += tot[1][k];
+        }
+        fin(it.sc[b], t0, t1);
+        it.sc[b].counter = 0u;
+    }
+}
+
+__device__ __forceinline__ bool finite(double v) { return isfinite(v); }
+
+__device__ __forceinline__ void fail_numeric(SolveScalars& s) {
+    s.status = MRI_ENUMERIC;
+    s.admm_active = 0;
+    s.cg_active = 0;
+}
+
+// ---- initialisation: rho = x0 (or 0), eta = 0, scalars reset ---------------
+__global__ __launch_bounds__(kVecThreads) void k_solve_init(const SolveTable tab) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    if (l.valid) {
+        const int64_t o = (int64_t)l.b * it.npix + l.pix;
+        const float2 v = it.x0 ? it.x0[o] : make_float2(0.f, 0.f);
+        it.rho[o] = v;
+        it.rho0[o] = v;
+        const int64_t e = (int64_t)l.b * 2 * it.npix + l.pix;
+        it.eta[e] = make_float2(0.f, 0.f);
+        it.eta[e + it.npix] = make_float2(0.f, 0.f);
+    }
+    if (l.blk == 0 && threadIdx.x == 0) {
+        SolveScalars& s = it.sc[l.b];
+        s.tau = s.alpha_cg = s.beta_cg = s.pap = 0.0;
+        s.alpha_admm = 1.0;
+        s.admm_active = 1;
+        s.cg_active = 0;
+        s.admm_iters = 0;
+        s.cg_steps = 0;
+        s.status = MRI_OK;
+        s.counter = 0u;
+    }
+}
+
+// ---- eq. (9)-(10): mu = S_{lambda/beta}(Theta rho + eta) ---------------------
+__global__ __launch_bounds__(kVecThreads) void k_mu(const SolveTable tab) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    if (!it.sc[l.b].admm_active || !l.valid) return;
+    const int64_t base = (int64_t)l.b * it.npix;
+    const float2* rho = it.rho + base;
+    const Nb n = neighbours(l.pix, it.nx, it.ny);
+    const float2 r0 = rho[l.pix];
+    const int64_t e = (int64_t)l.b * 2 * it.npix + l.pix;
+    float2 z[2];
+    z[0] = cadd(csub(rho[n.xp], r0), it.eta[e]);
+    z[1] = cadd(csub(rho[n.yp], r0), it.eta[e + it.npix]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float mag = sqrtf(z[c].x * z[c].x + z[c].y * z[c].y);
+        const float sc = mag > it.thr ? 1.0f - it.thr / mag : 0.0f;
+        it.mu[e + c * it.npix] = cscale(z[c], sc);
+    }
+}
+
+// ---- eq. (13): b = F^H d + (beta/2) Theta^H (mu - eta) -----------------------
+__global__ __launch_bounds__(kVecThreads) void k_rhs(const SolveTable tab) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    if (!it.sc[l.b].admm_active || !l.valid) return;
+    const int64_t e = (int64_t)l.b * 2 * it.npix;
+    const float2* mu0 = it.mu + e;
+    const float2* mu1 = mu0 + it.npix;
+    const float2* et0 = it.eta + e;
+    const float2* et1 = et0 + it.npix;
+    const Nb n = neighbours(l.pix, it.nx, it.ny);
+    const int64_t p = l.pix;
+    // Theta^H g = g0(i, j-1) - g0(i, j) + g1(i-1, j) - g1(i, j), g = mu - eta
+    const float2 g0m = csub(mu0[n.xm], et0[n.xm]), g0 = csub(mu0[p], et0[p]);
+    const float2 g1m = csub(mu1[n.ym], et1[n.ym]), g1 = csub(mu1[p], et1[p]);
+    const float2 th = cadd(csub(g0m, g0), csub(g1m, g1));
+    const int64_t o = (int64_t)l.b * it.npix + p;
+    it.b[o] = cadd(it.fhd[o], cscale(th, it.half_beta));
+}
+
+// ---- finish one application of A (or F^H d) from the adjoint's partials ------
+// kFinishFhd:    fhd = sum of partials
+// kFinishCgInit: q = A src; r = b - q; p = r; xnew = src; tau = r^H r   (Alg. 2 start)
+// kFinishCgStep: q = A p; pAp = Re(p^H q)                               (Alg. 2 step)
+// with A v = F^H F v + (beta/2) Theta^H Theta v and Theta^H Theta v the
+// periodic 5-point stencil 4 v - (four neighbours).
+__global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab, int mode) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    SolveScalars& sc = it.sc[l.b];
+    if (mode == kFinishCgInit && !sc.admm_active) return;
+    if (mode == kFinishCgStep && !sc.cg_active) return;
+    const int64_t base = (int64_t)l.b * it.npix;
+    float2 acc = make_float2(0.f, 0.f);
+    double v0 = 0.0;
+    if (l.valid) {
+        double sr = 0.0, si = 0.0;
+        const int64_t stride = (int64_t)it.nb * it.npix;
+        for (int s = 0; s < it.ksplit; ++s) {
+            const float2 v = it.part[s * stride + base + l.pix];
+            sr += v.x;
+            si += v.y;
+        }
+        acc = make_float2((float)sr, (float)si);
+        if (mode == kFinishFhd) {
+            it.fhd[base + l.pix] = acc;
+        } else {
+            const float2* src = mode == kFinishCgStep ? it.p + base : (it.warm ? it.rho + base : it.rho0 + base);
+            const Nb n = neighbours(l.pix, it.nx, it.ny);
+            const float2 c = src[l.pix];
+            float2 lap = cscale(c, 4.0f);
+            lap = csub(lap, src[n.xp]);
+            lap = csub(lap, src[n.xm]);
+            lap = csub(lap, src[n.yp]);
+            lap = csub(lap, src[n.ym]);
+            const float2 q = cadd(acc, cscale(lap, it.half_beta));
+            if (mode == kFinishCgStep) {
+                it.q[base + l.pix] = q;
+                v0 = (double)c.x * q.x + (double)c.y * q.y;
+            } else {
+                const float2 r = csub(it.b[base + l.pix], q);
+                it.r[base + l.pix] = r;
+                it.p[base + l.pix] = r;
+                it.xnew[base + l.pix] = c;
+                v0 = cnorm2(r);
+            }
+        }
+    }
+    if (mode == kFinishFhd) return;
+    const double atol2 = it.atol2;
+    if (mode == kFinishCgInit) {
+        reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2](SolveScalars& s, double t0, double) {
+            if (!finite(t0)) { fail_numeric(s); return; }
+            s.tau = t0;
+            s.cg_active = t0 > atol2 ? 1 : 0;
+        });
+    } else {
+        reduce2_finalize(v0, 0.0, it, l.b, l.blk, [](SolveScalars& s, double t0, double) {
+            if (!finite(t0)) { fail_numeric(s); return; }
+            s.pap = t0;
+            if (t0 > 0.0) {
+                s.alpha_cg = s.tau / t0;
+            } else {
+                s.cg_active = 0;    // breakdown: d^H A d <= 0
+            }
+        });
+    }
+}
+
+// ---- Alg. 2 step: x += alpha d; r -= alpha A d; tau' = r^H r ------------------
+__global__ __launch_bounds__(kVecThreads) void k_cg_update(const SolveTable tab) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    const SolveScalars& sc = it.sc[l.b];
+    if (!sc.cg_active) return;
+    const float a = (float)sc.alpha_cg;
+    double v0 = 0.0;
+    if (l.valid) {
+        const int64_t o = (int64_t)l.b * it.npix + l.pix;
+        const float2 p = it.p[o], q = it.q[o];
+        float2 x = it.xnew[o], r = it.r[o];
+        x = make_float2(fmaf(a, p.x, x.x), fmaf(a, p.y, x.y));
+        r = make_float2(fmaf(-a, q.x, r.x), fmaf(-a, q.y, r.y));
+        it.xnew[o] = x;
+        it.r[o] = r;
+        v0 = cnorm2(r);
+    }
+    const double atol2 = it.atol2;
+    reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2](SolveScalars& s, double t0, double) {
+        if (!finite(t0)) { fail_numeric(s); return; }
+        s.beta_cg = t0 / s.tau;
+        s.tau = t0;
+        s.cg_steps += 1;
+        s.cg_active = t0 > atol2 ? 1 : 0;
+    });
+}
+
+// ---- Alg. 2 direction: d = r + (tau'/tau) d -----------------------------------
+__global__ __launch_bounds__(kVecThreads) void k_cg_dir(const SolveTable tab) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    const SolveScalars& sc = it.sc[l.b];
+    if (!sc.cg_active || !l.valid) return;
+    const float bc = (float)sc.beta_cg;
+    const int64_t o = (int64_t)l.b * it.npix + l.pix;
+    const float2 r = it.r[o], p = it.p[o];
+    it.p[o] = make_float2(fmaf(bc, p.x, r.x), fmaf(bc, p.y, r.y));
+}
+
+// ---- eq. (8) and Alg. 4: eta += Theta rho' - mu; alpha; rho = rho' ------------
+__global__ __launch_bounds__(kVecThreads) void k_dual(const SolveTable tab) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    if (!it.sc[l.b].admm_active) return;
+    double num = 0.0, den = 0.0;
+    if (l.valid) {
+        const int64_t base = (int64_t)l.b * it.npix;
+        const float2* xn = it.xnew + base;
+        const Nb n = neighbours(l.pix, it.nx, it.ny);
+        const float2 c = xn[l.pix];
+        const int64_t e = (int64_t)l.b * 2 * it.npix + l.pix;
+        const float2 d0 = csub(xn[n.xp], c), d1 = csub(xn[n.yp], c);
+        it.eta[e] = cadd(it.eta[e], csub(d0, it.mu[e]));
+        it.eta[e + it.npix] = cadd(it.eta[e + it.npix], csub(d1, it.mu[e + it.npix]));
+        const float2 old = it.rho[base + l.pix];
+        num = cnorm2(csub(c, old));
+        den = cnorm2(old);
+        it.rho[base + l.pix] = c;
+    }
+    const double rtol2 = it.rtol2;
+    reduce2_finalize(num, den, it, l.b, l.blk, [rtol2](SolveScalars& s, double t0, double t1) {
+        if (!finite(t0) || !finite(t1)) { fail_numeric(s); return; }
+        const double a = t1 > 0.0 ? t0 / t1 : (t0 > 0.0 ? 1.0 : 0.0);
+        s.alpha_admm = a;
+        s.admm_iters += 1;
+        if (!(a > rtol2)) {
+            s.admm_active = 0;
+            s.cg_active = 0;
+        }
+    });
+}
+
+// ---- output and per-slice report ---------------------------------------------
+__global__ __launch_bounds__(kVecThreads) void k_solve_final(const SolveTable tab) {
+    const Loc l = locate(tab);
+    const SolveItem& it = tab.it[l.item];
+    if (l.valid) {
+        const int64_t o = (int64_t)l.b * it.npix + l.pix;
+        it.x_out[o] = it.rho[o];
+    }
+    if (it.stats && l.blk == 0 && threadIdx.x == 0) {
+        const SolveScalars& s = it.sc[l.b];
+        mri_admm_stats st;
+        st.admm_iters_run = s.admm_iters;
+        st.cg_steps_run = s.cg_steps;
+        st.alpha = s.alpha_admm;
+        st.tau = s.tau;
+        st.status = s.status;
+        st.pad = 0;
+        it.stats[l.b] = st;
+    }
+}
+
+// ---- plain kernels behind the single-operator entry points ------------------
+__global__ __launch_bounds__(kVecThreads) void k_sum_partials(const float2* __restrict__ part, int ksplit,
+                                                              int64_t n, float2* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < ksplit; ++s) {
+        const float2 v = part[s * n + i];
+        sr += v.x;
+        si += v.y;
+    }
+    out[i] = make_float2((float)sr, (float)si);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_tv_forward(int nx, int ny, int64_t n, const float2* __restrict__ x,
+                                                            float2* __restrict__ g) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t npix = (int64_t)nx * ny;
+    const int64_t b = i / npix, p = i - b * npix;
+    const float2* xb = x + b * npix;
+    const Nb nb = neighbours(p, nx, ny);
+    const float2 c = xb[p];
+    g[2 * b * npix + p] = csub(xb[nb.xp], c);
+    g[2 * b * npix + npix + p] = csub(xb[nb.yp], c);
+}
+
+__global__ __launch_bounds__(kVecThreads) void k_tv_adjoint(int nx, int ny, int64_t n, const float2* __restrict__ g,
+                                                            float2* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t npix = (int64_t)nx * ny;
+    const int64_t b = i / npix, p = i - b * npix;
+    const float2* g0 = g + 2 * b * npix;
+    const float2* g1 = g0 + npix;
+    const Nb nb = neighbours(p, nx, ny);
+    x[i] = cadd(csub(g0[nb.xm], g0[p]), csub(g1[nb.ym], g1[p]));
+}
+
+inline dim3 grid_of(const SolveTable& t) { return dim3(t.total_blocks); }
+
+}  // namespace
+
+hipError_t launch_solve_init(const SolveTable& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_init, grid_of(t), dim3(kVecThreads), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_mu(const SolveTable& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_mu, grid_of(t), dim3(kVecThreads), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_rhs(const SolveTable& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_rhs, grid_of(t), dim3(kVecThreads), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_adj_finish(const SolveTable& t, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_finish, grid_of(t), dim3(kVecThreads), 0, s, t, mode);
+    return hipGetLastError();
+}
+hipError_t launch_cg_update(const SolveTable& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update, grid_of(t), dim3(kVecThreads), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_cg_dir(const SolveTable& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_dir, grid_of(t), dim3(kVecThreads), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_dual(const SolveTable& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_dual, grid_of(t), dim3(kVecThreads), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_solve_final(const SolveTable& t, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_final, grid_of(t), dim3(kVecThreads), 0, s, t);
+    return hipGetLastError();
+}
+hipError_t launch_sum_partials(const float2* part, int ksplit, int64_t n, float2* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_partials, dim3((unsigned)ceil_div(n, kVecThreads)), dim3(kVecThreads), 0, s,
+                       part, ksplit, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_tv_forward(int nx, int ny, int nb, const float2* x, float2* g, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nb;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_forward, dim3((unsigned)ceil_div(n, kVecThreads)), dim3(kVecThreads), 0, s,
+                       nx, ny, n, x, g);
+    return hipGetLastError();
+}
+hipError_t launch_tv_adjoint(int nx, int ny, int nb, const float2* g, float2* x, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * nb;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_adjoint, dim3((unsigned)ceil_div(n, kVecThreads)), dim3(kVecThreads), 0, s,
+                       nx, ny, n, g, x);
+    return hipGetLastError();
+}
+
+}  // namespace mri

@@ -1,0 +1,278 @@
+"""ctypes binding of libmriadmm (C ABI in include/mri_admm.h).
+
+Argument marshalling only: tensors must already live on the GPU; every step
+of the computation runs in the library's HIP kernels on the current torch
+stream.  The library is loaded on first use and a missing build raises --
+there is no CPU fallback.
+
+Shapes (complex64 unless noted):
+  image  [B, ny, nx]          smaps [nc, ny, nx] or [B, nc, ny, nx]
+  traj   [nk, 2] or [B, nk, 2] float64, radians per pixel, column 0 <-> x
+  data   [B, nc, nk]          grad  [B, 2, ny, nx]
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmriadmm.so")
+
+FP32 = 0
+BF16X3 = 1
+PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3}
+
+OP_FORWARD, OP_ADJOINT, OP_ADMM = 0, 1, 2
+
+ERRORS = {0: "MRI_OK", -1: "MRI_EINVAL", -2: "MRI_ENOMEM", -3: "MRI_EHIP",
+          -4: "MRI_ENOTSUP", -5: "MRI_ENUMERIC"}
+
+
+class MriShape(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("ncoils", ctypes.c_int32),
+                ("nk", ctypes.c_int64), ("batch", ctypes.c_int32),
+                ("traj_batched", ctypes.c_int32), ("smaps_batched", ctypes.c_int32)]
+
+
+class MriAdmmParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("beta", ctypes.c_double),
+                ("admm_iters", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("cg_warm_start", ctypes.c_int32)]
+
+
+class MriAdmmStats(ctypes.Structure):
+    _fields_ = [("admm_iters_run", ctypes.c_int32), ("cg_steps_run", ctypes.c_int32),
+                ("alpha", ctypes.c_double), ("tau", ctypes.c_double),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+STATS_BYTES = ctypes.sizeof(MriAdmmStats)
+
+EXPORTS = ["nudft_forward", "nudft_adjoint", "tv_forward", "tv_adjoint", "admm_solve",
+           "mri_workspace_bytes", "mri_strerror", "mri_last_hip_error"]
+
+_lib = None
+
+
+class MriError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{where}: {ERRORS.get(code, code)}{(' - ' + detail) if detail else ''}")
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2006_14080_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    shp = ctypes.POINTER(MriShape)
+    prm = ctypes.POINTER(MriAdmmParams)
+    lib.nudft_forward.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.nudft_adjoint.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.tv_forward.argtypes = [shp, vp, vp, vp]
+    lib.tv_adjoint.argtypes = [shp, vp, vp, vp]
+    lib.admm_solve.argtypes = [shp, vp, vp, vp, vp, prm, vp, vp, vp, sz, vp]
+    lib.mri_workspace_bytes.argtypes = [shp, i32, prm]
+    lib.mri_workspace_bytes.restype = sz
+    lib.mri_strerror.argtypes = [i32]
+    lib.mri_strerror.restype = ctypes.c_char_p
+    lib.mri_last_hip_error.argtypes = []
+    lib.mri_last_hip_error.restype = ctypes.c_char_p
+    for name in ["nudft_forward", "nudft_adjoint", "tv_forward", "tv_adjoint", "admm_solve"]:
+        getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        detail = ""
+        if rc == -3:
+            detail = load().mri_last_hip_error().decode()
+        raise MriError(rc, where, detail)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _need(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def make_shape(nx, ny, nc, nk, batch=1, traj_batched=False, smaps_batched=False) -> MriShape:
+    return MriShape(int(nx), int(ny), int(nc), int(nk), int(batch), int(traj_batched), int(smaps_batched))
+
+
+def shape_of(image_shape, smaps: torch.Tensor, traj: torch.Tensor) -> MriShape:
+    b, ny, nx = image_shape
+    smaps_batched = smaps.dim() == 4
+    traj_batched = traj.dim() == 3
+    nc = smaps.shape[-3]
+    nk = traj.shape[-2]
+    if tuple(smaps.shape[-2:]) != (ny, nx):
+        raise ValueError("smaps do not match the image grid")
+    if smaps_batched and smaps.shape[0] != b:
+        raise ValueError("batched smaps must have one map set per slice")
+    if traj_batched and traj.shape[0] != b:
+        raise ValueError("batched traj must have one trajectory per slice")
+    if traj.shape[-1] != 2:
+        raise ValueError("traj must be [..., nk, 2]")
+    return make_shape(nx, ny, nc, nk, b, traj_batched, smaps_batched)
+
+
+def workspace_bytes(shape: MriShape, op: int, params: Optional[MriAdmmParams] = None) -> int:
+    lib = load()
+    return int(lib.mri_workspace_bytes(ctypes.byref(shape), op,
+                                       ctypes.byref(params) if params is not None else None))
+
+
+def _workspace(shape, op, params=None, device=None):
+    n = workspace_bytes(shape, op, params)
+    if n == 0:
+        return None, 0
+    return torch.empty(n, dtype=torch.uint8, device=device), n
+
+
+def nudft_forward(image: torch.Tensor, smaps: torch.Tensor, traj: torch.Tensor,
+                  precision: int = FP32, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = F(image), eq. (1): [B, ny, nx] -> [B, nc, nk]."""
+    lib = load()
+    _need(image, torch.complex64, "image")
+    _need(smaps, torch.complex64, "smaps")
+    _need(traj, torch.float64, "traj")
+    sh = shape_of(image.shape, smaps, traj)
+    if out is None:
+        out = torch.empty((sh.batch, sh.ncoils, sh.nk), dtype=torch.complex64, device=image.device)
+    _need(out, torch.complex64, "out")
+    ws, n = _workspace(sh, OP_FORWARD, device=image.device)
+    _check(lib.nudft_forward(ctypes.byref(sh), _ptr(image), _ptr(smaps), _ptr(traj), _ptr(out),
+                             precision, _ptr(ws), n, _stream()), "nudft_forward")
+    return out
+
+
+def nudft_adjoint(data: torch.Tensor, smaps: torch.Tensor, traj: torch.Tensor, ny: int, nx: int,
+                  precision: int = FP32, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = F^H(data): [B, nc, nk] -> [B, ny, nx]."""
+    lib = load()
+    _need(data, torch.complex64, "data")
+    _need(smaps, torch.complex64, "smaps")
+    _need(traj, torch.float64, "traj")
+    b = data.shape[0]
+    sh = shape_of((b, ny, nx), smaps, traj)
+    if tuple(data.shape) != (b, sh.ncoils, sh.nk):
+        raise ValueError("data must be [B, nc, nk]")
+    if out is None:
+        out = torch.empty((b, ny, nx), dtype=torch.complex64, device=data.device)
+    _need(out, torch.complex64, "out")
+    ws, n = _workspace(sh, OP_ADJOINT, device=data.device)
+    _check(lib.nudft_adjoint(ctypes.byref(sh), _ptr(data), _ptr(smaps), _ptr(traj), _ptr(out),
+                             precision, _ptr(ws), n, _stream()), "nudft_adjoint")
+    return out
+
+
+def tv_forward(image: torch.Tensor) -> torch.Tensor:
+    """g = Theta(image): [B, ny, nx] -> [B, 2, ny, nx]."""
+    lib = load()
+    _need(image, torch.complex64, "image")
+    b, ny, nx = image.shape
+    sh = make_shape(nx, ny, 1, 1, b)
+    g = torch.empty((b, 2, ny, nx), dtype=torch.complex64, device=image.device)
+    _check(lib.tv_forward(ctypes.byref(sh), _ptr(image), _ptr(g), _stream()), "tv_forward")
+    return g
+
+
+def tv_adjoint(grad: torch.Tensor) -> torch.Tensor:
+    """x = Theta^H(grad): [B, 2, ny, nx] -> [B, ny, nx]."""
+    lib = load()
+    _need(grad, torch.complex64, "grad")
+    b, two, ny, nx = grad.shape
+    if two != 2:
+        raise ValueError("grad must be [B, 2, ny, nx]")
+    sh = make_shape(nx, ny, 1, 1, b)
+    x = torch.empty((b, ny, nx), dtype=torch.complex64, device=grad.device)
+    _check(lib.tv_adjoint(ctypes.byref(sh), _ptr(grad), _ptr(x), _stream()), "tv_adjoint")
+    return x
+
+
+@dataclasses.dataclass
+class AdmmParams:
+    lam: float
+    beta: float
+    admm_iters: int
+    cg_iters: int
+    rtol: float = 0.0
+    atol: float = 0.0
+    precision: int = FP32
+    cg_warm_start: bool = True
+
+    def c(self) -> MriAdmmParams:
+        return MriAdmmParams(float(self.lam), float(self.beta), int(self.admm_iters), int(self.cg_iters),
+                             float(self.rtol), float(self.atol), int(self.precision), int(self.cg_warm_start))
+
+
+class AdmmSolver:
+    """Reusable admm_solve launcher: owns its workspace, so repeated solves of
+    one shape allocate nothing after construction."""
+
+    def __init__(self, shape: MriShape, params: AdmmParams, device="cuda"):
+        self.shape = shape
+        self.params = params
+        self._cp = params.c()
+        n = workspace_bytes(shape, OP_ADMM, self._cp)
+        self.ws = torch.empty(max(n, 1), dtype=torch.uint8, device=device)
+        self.ws_bytes = n
+        self.stats_buf = torch.zeros(shape.batch * STATS_BYTES, dtype=torch.uint8, device=device)
+
+    def solve(self, smaps, traj, data, x0=None, out=None) -> torch.Tensor:
+        lib = load()
+        sh = self.shape
+        _need(smaps, torch.complex64, "smaps")
+        _need(traj, torch.float64, "traj")
+        _need(data, torch.complex64, "data")
+        if x0 is not None:
+            _need(x0, torch.complex64, "x0")
+        if out is None:
+            out = torch.empty((sh.batch, sh.ny, sh.nx), dtype=torch.complex64, device=data.device)
+        _need(out, torch.complex64, "out")
+        _check(lib.admm_solve(ctypes.byref(sh), _ptr(smaps), _ptr(traj), _ptr(data), _ptr(x0),
+                              ctypes.byref(self._cp), _ptr(out), _ptr(self.stats_buf),
+                              _ptr(self.ws), self.ws_bytes, _stream()), "admm_solve")
+        return out
+
+    def stats(self):
+        """Per-slice solve report (synchronises the stream)."""
+        raw = self.stats_buf.cpu().numpy().tobytes()
+        out = []
+        for b in range(self.shape.batch):
+            s = MriAdmmStats.from_buffer_copy(raw[b * STATS_BYTES:(b + 1) * STATS_BYTES])
+            out.append(dict(admm_iters=s.admm_iters_run, cg_steps=s.cg_steps_run, alpha=s.alpha,
+                            tau=s.tau, status=s.status))
+        return out
+
+
+def admm_solve(smaps, traj, data, ny, nx, params: AdmmParams, x0=None):
+    """One-shot ADMM-TV reconstruction (Alg. 4).  Returns (image, stats)."""
+    sh = shape_of((data.shape[0], ny, nx), smaps, traj)
+    solver = AdmmSolver(sh, params, device=data.device)
+    img = solver.solve(smaps, traj, data, x0)
+    return img, solver.stats()

@@ -1,0 +1,98 @@
+"""The C ABI library loads, exports every entry point include/mri_admm.h
+declares, agrees with the binding on struct layouts, and rejects bad
+arguments on the host before touching the GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2006_14080_amd import mri
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mri_admm.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mri.LIB_PATH):
+        pytest.fail("libmriadmm.so has not been built (run __graft_entry__.build())")
+    return mri.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for n in ["nudft_forward", "nudft_adjoint", "tv_forward", "tv_adjoint", "admm_solve",
+              "mri_workspace_bytes", "mri_strerror"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts():
+    assert ctypes.sizeof(mri.MriShape) == 40
+    assert mri.MriShape.nk.offset == 16
+    assert ctypes.sizeof(mri.MriAdmmParams) == 48
+    assert ctypes.sizeof(mri.MriAdmmStats) == 32
+
+
+def test_strerror(lib):
+    assert lib.mri_strerror(0) == b"success"
+    assert b"invalid" in lib.mri_strerror(-1)
+    assert b"unknown" in lib.mri_strerror(12345)
+
+
+def test_workspace_sizes(lib):
+    sh = mri.make_shape(256, 256, 8, 32768)
+    p = mri.AdmmParams(1e-3, 1.0, 30, 5).c()
+    assert mri.workspace_bytes(sh, mri.OP_FORWARD) == 0
+    adj = mri.workspace_bytes(sh, mri.OP_ADJOINT)
+    assert adj >= 256 * 256 * 8 and adj % 256 == 0
+    total = mri.workspace_bytes(sh, mri.OP_ADMM, p)
+    assert total > 12 * 256 * 256 * 8 + 8 * 32768 * 8
+    bad = mri.make_shape(0, 256, 8, 32768)
+    assert mri.workspace_bytes(bad, mri.OP_ADMM, p) == 0
+
+
+@pytest.mark.parametrize("field,value", [("nx", 0), ("ny", -1), ("ncoils", 0), ("nk", 0),
+                                         ("batch", 0), ("traj_batched", 2), ("nx", 4096)])
+def test_bad_shapes_rejected_on_host(lib, field, value):
+    sh = mri.make_shape(8, 8, 2, 16)
+    setattr(sh, field, value)
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+    rc = lib.nudft_forward(ctypes.byref(sh), fake, fake, fake, fake, 0, None, 0, None)
+    assert rc == -1
+
+
+def test_bad_params_rejected_on_host(lib):
+    sh = mri.make_shape(8, 8, 2, 16)
+    fake = ctypes.c_void_p(0x1000)
+    for kw in [dict(lam=-1.0), dict(beta=0.0), dict(admm_iters=-1), dict(cg_iters=-2),
+               dict(rtol=-1e-3), dict(precision=7)]:
+        args = dict(lam=1e-3, beta=1.0, admm_iters=2, cg_iters=2)
+        args.update(kw)
+        p = mri.AdmmParams(**args).c()
+        rc = lib.admm_solve(ctypes.byref(sh), fake, fake, fake, None, ctypes.byref(p), fake, None,
+                            fake, 1 << 30, None)
+        assert rc == -1, kw
+    p = mri.AdmmParams(1e-3, 1.0, 2, 2).c()
+    rc = lib.admm_solve(ctypes.byref(sh), fake, fake, fake, None, ctypes.byref(p), fake, None, fake, 16, None)
+    assert rc == -2   # workspace too small
+
+
+def test_null_pointers_rejected(lib):
+    sh = mri.make_shape(8, 8, 2, 16)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.nudft_forward(ctypes.byref(sh), None, fake, fake, fake, 0, None, 0, None) == -1
+    assert lib.tv_forward(ctypes.byref(sh), None, fake, None) == -1
+    assert lib.nudft_adjoint(ctypes.byref(sh), fake, fake, fake, fake, 0, None, 0, None) == -2

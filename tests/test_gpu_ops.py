@@ -1,0 +1,149 @@
+"""GPU parity of the single operators (nudft_forward, nudft_adjoint, tv_*)
+against the FP64 oracle, through the C ABI.
+
+Bar: relative L2 error <= 1e-5 per NUDFT in FP32 (element by element over the
+whole output); TV transforms are exact up to one FP32 rounding per element.
+Sizes span several tiles (64 samples / 256 rows for the forward, 64 x 32
+pixels and 8-coil groups for the adjoint) with ragged tails; full-size
+shapes are checked on sampled outputs that the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nudft as onudft
+from oracle import tv as otv
+from paper_2006_14080_amd import mri, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _inputs(nx, ny, nc, nk, batch, seed, traj_batched=False, smaps_batched=False):
+    img = synth.random_complex((batch, ny, nx), seed)
+    sm = synth.random_complex((batch, nc, ny, nx) if smaps_batched else (nc, ny, nx), seed + 1)
+    if traj_batched:
+        tr = np.stack([synth.random_trajectory(nk, seed + 2 + b) for b in range(batch)])
+    else:
+        tr = synth.random_trajectory(nk, seed + 2)
+    dat = synth.random_complex((batch, nc, nk), seed + 3)
+    return img, sm, tr, dat
+
+
+def _per_slice(a, b, batched):
+    return a[b] if batched else a
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+SHAPES = [
+    # nx, ny, nc, nk, batch
+    (32, 32, 4, 1024, 1),
+    (5, 7, 3, 77, 2),
+    (37, 33, 2, 130, 1),
+    (64, 48, 9, 200, 3),
+    (20, 300, 3, 70, 1),     # two 256-row passes in the forward
+    (130, 70, 17, 333, 1),   # three coil groups and ragged tiles in the adjoint
+    (1, 1, 1, 1, 1),         # degenerate single pixel / sample
+]
+
+
+@pytest.mark.parametrize("nx,ny,nc,nk,batch", SHAPES)
+def test_forward_parity(nx, ny, nc, nk, batch):
+    img, sm, tr, _ = _inputs(nx, ny, nc, nk, batch, 10)
+    got = mri.nudft_forward(_gpu(img), _gpu(sm), _gpu(tr)).cpu().numpy()
+    ref = np.stack([onudft.forward(img[b], sm, tr) for b in range(batch)])
+    assert got.shape == ref.shape
+    assert rel(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny,nc,nk,batch", SHAPES)
+def test_adjoint_parity(nx, ny, nc, nk, batch):
+    _, sm, tr, dat = _inputs(nx, ny, nc, nk, batch, 20)
+    got = mri.nudft_adjoint(_gpu(dat), _gpu(sm), _gpu(tr), ny, nx).cpu().numpy()
+    ref = np.stack([onudft.adjoint(dat[b], sm, tr) for b in range(batch)])
+    assert rel(got, ref) <= TOL
+
+
+def test_batched_maps_and_trajectories():
+    nx, ny, nc, nk, batch = 24, 20, 3, 150, 3
+    img, sm, tr, dat = _inputs(nx, ny, nc, nk, batch, 30, traj_batched=True, smaps_batched=True)
+    f = mri.nudft_forward(_gpu(img), _gpu(sm), _gpu(tr)).cpu().numpy()
+    a = mri.nudft_adjoint(_gpu(dat), _gpu(sm), _gpu(tr), ny, nx).cpu().numpy()
+    for b in range(batch):
+        assert rel(f[b], onudft.forward(img[b], sm[b], tr[b])) <= TOL
+        assert rel(a[b], onudft.adjoint(dat[b], sm[b], tr[b])) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny", [(8, 8), (16, 12), (7, 9)])
+def test_cartesian_trajectory_matches_oracle_fft_case(nx, ny):
+    img = synth.random_complex((1, ny, nx), 40)
+    tr = synth.cartesian_trajectory(nx, ny)
+    one = np.ones((1, ny, nx), np.complex64)
+    got = mri.nudft_forward(_gpu(img), _gpu(one), _gpu(tr)).cpu().numpy()[0, 0]
+    ref = onudft.forward(img[0], one, tr)[0]
+    assert rel(got, ref) <= TOL
+
+
+def test_gpu_adjoint_identity():
+    nx, ny, nc, nk = 48, 40, 5, 700
+    img, sm, tr, dat = _inputs(nx, ny, nc, nk, 1, 50)
+    f = mri.nudft_forward(_gpu(img), _gpu(sm), _gpu(tr)).cpu().numpy().astype(np.complex128)
+    a = mri.nudft_adjoint(_gpu(dat), _gpu(sm), _gpu(tr), ny, nx).cpu().numpy().astype(np.complex128)
+    lhs = np.vdot(f.ravel(), dat.ravel().astype(np.complex128))
+    rhs = np.vdot(img.ravel().astype(np.complex128), a.ravel())
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+def test_bitwise_reproducible():
+    nx, ny, nc, nk = 96, 64, 6, 3000
+    img, sm, tr, dat = _inputs(nx, ny, nc, nk, 1, 60)
+    g = [_gpu(a) for a in (img, sm, tr, dat)]
+    f1 = mri.nudft_forward(g[0], g[1], g[2])
+    f2 = mri.nudft_forward(g[0], g[1], g[2])
+    a1 = mri.nudft_adjoint(g[3], g[1], g[2], ny, nx)
+    a2 = mri.nudft_adjoint(g[3], g[1], g[2], ny, nx)
+    assert torch.equal(f1, f2) and torch.equal(a1, a2)
+
+
+@pytest.mark.parametrize("wl,batch", [(synth.ADMM256, 1), (synth.SLICES384, 2)])
+def test_full_size_sampled(wl, batch):
+    # Full workload shapes; the oracle recomputes 96 sampled outputs one by one.
+    rng = np.random.default_rng(70)
+    p = synth.make_problem(wl, batch=batch)
+    img = p.truth + synth.random_complex(p.truth.shape, 71) * np.complex64(0.1)
+    gi, gs, gt = _gpu(img), _gpu(p.smaps), _gpu(p.traj)
+    f = mri.nudft_forward(gi, gs, gt).cpu().numpy()
+    dat = synth.random_complex((batch, wl.nc, wl.nk), 72)
+    a = mri.nudft_adjoint(_gpu(dat), gs, gt, wl.ny, wl.nx).cpu().numpy()
+    for b in range(batch):
+        coils = rng.integers(0, wl.nc, 48)
+        ks = rng.integers(0, wl.nk, 48)
+        ks[:4] = [0, wl.nk - 1, wl.nk // 2, 63]
+        ref = onudft.forward_samples(img[b], p.smaps, p.traj, coils, ks)
+        assert rel(f[b][coils, ks], ref) <= TOL
+        rows = rng.integers(0, wl.ny, 48)
+        cols = rng.integers(0, wl.nx, 48)
+        rows[:2], cols[:2] = [0, wl.ny - 1], [wl.nx - 1, 0]
+        ref = onudft.adjoint_pixels(dat[b], p.smaps, p.traj, rows, cols)
+        assert rel(a[b][rows, cols], ref) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny,batch", [(32, 32, 1), (7, 5, 3), (1, 9, 2), (300, 2, 1)])
+def test_tv_parity(nx, ny, batch):
+    x = synth.random_complex((batch, ny, nx), 80)
+    g = synth.random_complex((batch, 2, ny, nx), 81)
+    gf = mri.tv_forward(_gpu(x)).cpu().numpy()
+    ga = mri.tv_adjoint(_gpu(g)).cpu().numpy()
+    for b in range(batch):
+        np.testing.assert_allclose(gf[b], otv.tv_forward(x[b]), rtol=0, atol=1e-6)
+        np.testing.assert_allclose(ga[b], otv.tv_adjoint(g[b]), rtol=0, atol=1e-6)
