@@ -1,0 +1,176 @@
+"""Benchmark: ADMM-TV reconstruction throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3]
+
+One step = one full admm_solve of the 256x256, 8-coil, 64x512-sample radial
+problem (30 ADMM iterations x 5 CG steps: 1 + 2*30*6 = 361 NUDFT calls),
+inputs resident in HBM.  value = ADMM iterations per second over the K timed
+steps.  Also reported:
+
+* roofline -- the dominant NUDFT kernel: algorithmic flop per launch
+  (8 * nk * nx * ny * nc) over its average launch time, measured with HIP
+  events on the stream it runs on, against the MI355X dense FP32 MFMA peak
+  (BF16 peak for the split-BF16 form, where each product costs three);
+* cpu_baseline -- the FP64 NumPy oracle timed on the host on a bounded sample
+  (one ADMM iteration with 5 CG steps of the same problem).
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}   # MI355X dense MFMA peaks
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--kernel-launches", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "nudft_traffic_admm256.json"),
+                    help="JSON with measured HBM bytes per launch of the NUDFT kernels (optional)")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, p):
+    """Oracle timed on one ADMM iteration (5 CG steps) of the same problem."""
+    from oracle import admm as oadmm
+    from oracle import nudft as onudft
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    data = (onudft.forward(p.truth[0], p.smaps, p.traj) + p.noise[0]).astype(np.complex64)
+    t0 = time.perf_counter()
+    oadmm.admm(data, p.smaps, p.traj, wl.lam, wl.beta, 1, wl.cg_iters)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "ADMM iters/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 ADMM iteration x {wl.cg_iters} CG (13 NUDFT calls incl. F^H d) of "
+                      f"{wl.name}, FP64 NumPy, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "k-space split is design-only in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2006_14080_amd import mri, synth
+
+    prec = mri.PRECISIONS[args.precision]
+    wl = synth.ADMM256
+    p = synth.make_problem(wl)
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    sm, tr, truth = g(p.smaps), g(p.traj), g(p.truth)
+    # Synthetic k-space data: F(phantom) on the GPU plus seeded complex noise.
+    data = mri.nudft_forward(truth, sm, tr, precision=mri.FP32)
+    data += g(p.noise.astype(np.complex64))
+    torch.cuda.synchronize()
+
+    params = mri.AdmmParams(wl.lam, wl.beta, wl.admm_iters, wl.cg_iters, precision=prec)
+    shape = mri.shape_of((1, wl.ny, wl.nx), sm, tr)
+    solver = mri.AdmmSolver(shape, params, device=dev)
+    out = torch.empty((1, wl.ny, wl.nx), dtype=torch.complex64, device=dev)
+
+    for _ in range(args.warmup):
+        solver.solve(sm, tr, data, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        solver.solve(sm, tr, data, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    st = solver.stats()[0]
+    if st["status"] != 0 or st["admm_iters"] != wl.admm_iters:
+        raise RuntimeError(f"solve did not run to completion: {st}")
+    iters_per_s = wl.admm_iters * args.steps / (ms_total / 1e3)
+
+    # Per-kernel timing of the two NUDFT operators at the solve's launch
+    # configuration (same kernels, tables and stream as inside admm_solve).
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(n):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / n
+
+    dtmp = torch.empty_like(data)
+    img = out.clone()
+    fwd_ms = timed(lambda: mri.nudft_forward(img, sm, tr, precision=prec, out=dtmp), args.kernel_launches)
+    adj_ms = timed(lambda: mri.nudft_adjoint(data, sm, tr, wl.ny, wl.nx, precision=prec, out=img),
+                   args.kernel_launches)
+    flop = wl.nudft_flop
+    dom_name, dom_ms = ("nudft_forward", fwd_ms) if fwd_ms >= adj_ms else ("nudft_adjoint", adj_ms)
+    achieved = flop / (dom_ms / 1e3) / 1e12
+    if prec == mri.BF16X3:
+        achieved_pipe = achieved * 3.0      # three BF16 products per real product
+    else:
+        achieved_pipe = achieved
+    peak = PEAK_TFLOPS[args.precision]
+    traffic = None
+    if os.path.exists(args.traffic):
+        try:
+            with open(args.traffic) as f:
+                traffic = json.load(f).get(args.precision, {}).get(dom_name)
+        except Exception:
+            traffic = None
+
+    rec = {
+        "metric": "ADMM iters/s (256x256, 8 coils, 64x512 radial samples, 30 ADMM x 5 CG)",
+        "value": iters_per_s,
+        "unit": "ADMM iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == mri.FP32 else "bf16x3",
+        "data": "synthetic (seeded ellipse phantom, Gaussian coil maps, golden-angle radial trajectory, "
+                "complex Gaussian noise 1e-3)",
+        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "coils": wl.nc, "spokes": wl.n_spokes,
+                   "readout": wl.n_readout, "admm_iters": wl.admm_iters, "cg_iters": wl.cg_iters,
+                   "lambda": wl.lam, "beta": wl.beta, "precision": args.precision,
+                   "nudft_calls_per_step": wl.nudft_calls},
+        "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": achieved_pipe, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved_pipe / peak, "traffic": traffic,
+                     "algorithmic_tflop_per_launch": flop / 1e12,
+                     "avg_launch_ms": dom_ms},
+        "kernels_ms": {"nudft_forward": fwd_ms, "nudft_adjoint": adj_ms,
+                       "fp32_equiv_tflops": {"nudft_forward": flop / fwd_ms / 1e9,
+                                             "nudft_adjoint": flop / adj_ms / 1e9}},
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(wl, p)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

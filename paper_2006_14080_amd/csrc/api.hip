@@ -83,9 +83,19 @@ NudftTable single_table(const NudftItem& it, int64_t ntiles) {
     return t;
 }
 
+size_t forward_ws(const mri_shape& s) {
+    return align_up(sizeof(float2) * (size_t)fwd_wimg_elems(s.nx, s.ny, s.ncoils, s.batch));
+}
+
+size_t adjoint_ws(const mri_shape& s) {
+    int32_t ks, kp;
+    adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, MRI_FP32, &ks, &kp);
+    return align_up(sizeof(float2) * (size_t)s.nx * s.ny * s.batch * adj_partial_planes(s.ncoils, ks));
+}
+
 // ---- ADMM workspace ---------------------------------------------------------
 struct AdmmLayout {
-    size_t rho, rho0, xnew, b, r, p, q, fhd, eta, mu, dtmp, part, red, sc, total;
+    size_t rho, rho0, xnew, b, r, p, q, fhd, eta, mu, dtmp, wimg, part, red, sc, total;
     int32_t ksplit, kper, nblk;
 };
 
@@ -107,17 +117,12 @@ AdmmLayout admm_layout(const mri_shape& s, int precision) {
     L.eta = o;  o += 2 * vec;
     L.mu = o;   o += 2 * vec;
     L.dtmp = o; o += align_up(sizeof(float2) * (size_t)s.ncoils * s.nk * s.batch);
-    L.part = o; o += align_up(sizeof(float2) * (size_t)npix * s.batch * L.ksplit);
+    L.wimg = o; o += forward_ws(s);
+    L.part = o; o += adjoint_ws(s);
     L.red = o;  o += align_up(sizeof(double) * 2 * (size_t)L.nblk * s.batch);
     L.sc = o;   o += align_up(sizeof(SolveScalars) * (size_t)s.batch);
     L.total = o;
     return L;
-}
-
-size_t adjoint_ws(const mri_shape& s) {
-    int32_t ks, kp;
-    adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, MRI_FP32, &ks, &kp);
-    return align_up(sizeof(float2) * (size_t)s.nx * s.ny * s.batch * ks);
 }
 
 template <class T>
@@ -135,7 +140,7 @@ extern "C" {
 size_t mri_workspace_bytes(const mri_shape* shape, int op, const mri_admm_params* params) {
     if (check_shape(shape) != MRI_OK) return 0;
     switch (op) {
-        case MRI_OP_FORWARD: return 0;
+        case MRI_OP_FORWARD: return forward_ws(*shape);
         case MRI_OP_ADJOINT: return adjoint_ws(*shape);
         case MRI_OP_ADMM: return admm_layout(*shape, params ? params->precision : MRI_FP32).total;
         default: return 0;
@@ -158,16 +163,19 @@ const char* mri_last_hip_error(void) { return g_last_hip.c_str(); }
 
 int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps, const double* traj,
                   mri_c32* y, int precision, void* ws, size_t ws_bytes, void* stream) {
-    (void)ws; (void)ws_bytes;
     int rc = check_shape(shape);
     if (rc) return rc;
     if ((rc = check_precision(precision))) return rc;
     if (!x || !smaps || !traj || !y) return MRI_EINVAL;
+    if (!ws || ws_bytes < forward_ws(*shape)) return MRI_ENOMEM;
     NudftItem it = base_item(*shape, reinterpret_cast<const float2*>(smaps), traj);
     it.img = reinterpret_cast<const float2*>(x);
+    it.wimg = static_cast<float2*>(ws);
     it.data = reinterpret_cast<float2*>(y);
     const NudftTable t = single_table(it, fwd_tiles(shape->nx, shape->ny, shape->ncoils, shape->nk, shape->batch));
-    MRI_HIP(launch_nudft_forward(t, precision, static_cast<hipStream_t>(stream)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    MRI_HIP(launch_coil_weight(t, s));
+    MRI_HIP(launch_nudft_forward(t, precision, s));
     return MRI_OK;
 }
 
@@ -186,7 +194,8 @@ int nudft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps
     const NudftTable t = single_table(it, adj_tiles_per_split(shape->nx, shape->ny, shape->batch) * it.ksplit);
     hipStream_t s = static_cast<hipStream_t>(stream);
     MRI_HIP(launch_nudft_adjoint(t, precision, s));
-    MRI_HIP(launch_sum_partials(it.part, it.ksplit, (int64_t)shape->nx * shape->ny * shape->batch,
+    MRI_HIP(launch_sum_partials(it.part, adj_partial_planes(shape->ncoils, it.ksplit),
+                                (int64_t)shape->nx * shape->ny * shape->batch,
                                 reinterpret_cast<float2*>(x), s));
     return MRI_OK;
 }
@@ -231,7 +240,7 @@ int admm_solve(const mri_shape* shape, const mri_c32* smaps, const double* traj,
     si.nb = sh.batch;
     si.nblk = L.nblk;
     si.block_begin = 0;
-    si.ksplit = L.ksplit;
+    si.ksplit = adj_partial_planes(sh.ncoils, L.ksplit);
     si.npix = npix;
     si.x0 = reinterpret_cast<const float2*>(x0);
     si.rho = at<float2>(ws, L.rho);
@@ -265,6 +274,7 @@ int admm_solve(const mri_shape* shape, const mri_c32* smaps, const double* traj,
     base.kper = L.kper;
     base.part = si.part;
     base.active_stride = flag_stride;
+    base.wimg = at<float2>(ws, L.wimg);
     const int64_t ftiles = fwd_tiles(sh.nx, sh.ny, sh.ncoils, sh.nk, sh.batch);
     const int64_t atiles = adj_tiles_per_split(sh.nx, sh.ny, sh.batch) * L.ksplit;
 
@@ -295,10 +305,12 @@ int admm_solve(const mri_shape* shape, const mri_c32* smaps, const double* traj,
     for (int m = 0; m < params->admm_iters; ++m) {
         MRI_HIP(launch_mu(st, s));
         MRI_HIP(launch_rhs(st, s));
+        MRI_HIP(launch_coil_weight(T_finit, s));
         MRI_HIP(launch_nudft_forward(T_finit, prec, s));
         MRI_HIP(launch_nudft_adjoint(T_ainit, prec, s));
         MRI_HIP(launch_adj_finish(st, kFinishCgInit, s));
         for (int j = 0; j < params->cg_iters; ++j) {
+            MRI_HIP(launch_coil_weight(T_fstep, s));
             MRI_HIP(launch_nudft_forward(T_fstep, prec, s));
             MRI_HIP(launch_nudft_adjoint(T_astep, prec, s));
             MRI_HIP(launch_adj_finish(st, kFinishCgStep, s));

@@ -24,8 +24,9 @@ struct NudftItem {
     const double* traj;  int64_t traj_bs;    // doubles per slice, 0 = shared
     const float2* smaps; int64_t smaps_bs;   // complex per slice, 0 = shared
     const float2* img;                       // [nb][ny][nx]   forward input
+    float2* wimg;                            // [nb][nc][ny][pitch] coil-weighted image (forward workspace)
     float2* data;                            // [nb][nc][nk]   forward output / adjoint input
-    float2* part;                            // [ksplit][nb][ny][nx] adjoint partial images
+    float2* part;                            // [ksplit * coil groups][nb][ny][nx] adjoint partial images
     const int32_t* active;                   // per-slice run flag (nullable): slice b runs iff
                                              // active[b * active_stride] != 0
     int32_t active_stride;
@@ -52,11 +53,17 @@ constexpr int kKStep = 8;          // complex K values per pipeline stage
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb);
+// Elements of the coil-weighted image the forward reads (rows padded to a K-step).
+int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb);
 int64_t adj_tiles_per_split(int nx, int ny, int nb);
+// Partial images the adjoint writes per slice: one per (sample split, group of 8 coils).
+int adj_partial_planes(int nc, int ksplit);
 // Choose the sample-range split of the adjoint for one problem.
 void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
                int32_t* ksplit, int32_t* kper);
 
+// Pre-pass of the forward for item 0 of t: wimg = smaps (.) img.
+hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s);
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s);
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s);
 

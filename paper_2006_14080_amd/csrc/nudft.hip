@@ -4,33 +4,41 @@
 // Both operators use the separable phase of Alg. 1,
 //   exp(-i (w0 x + w1 y)) = Ex[k][x] * Ey[k][y],
 // and never store a phase matrix: every phase tile is generated in LDS from
-// the trajectory, with the argument reduced in FP64 (device.h).
+// the trajectory (phase.h), one K-step ahead of the matrix cores.
 //
 // Forward, per slice b and coil g:  T[y][k] = sum_x I[y][x] Ex[k][x] with
-// I = s_g (.) x_b, then y[g][k] = sum_y T[y][k] Ey[k][y].  The product is a
-// complex GEMM with M = y, N = k (samples), K = x; the y-sum is the epilogue.
+// I = s_g (.) x_b (formed by a pre-pass, k_coil_weight), then
+// y[g][k] = sum_y T[y][k] Ey[k][y] in the epilogue.  GEMM M = y, N = k, K = x.
 //
 // Adjoint, per slice:  X_g[y][x] = sum_k W[(g,y)][k] conj(Ex[k][x]) with
-// W = y[g][k] conj(Ey[k][y]) generated as the A operand; then the epilogue
-// forms sum_g conj(s_g[y][x]) X_g[y][x].  M = (coil, y), N = x, K = samples,
-// split over sample ranges; partial images are summed in a fixed order by the
-// reduction kernel in solver.hip.
+// W = y[g][k] conj(Ey[k][y]) generated as the A operand; the epilogue forms
+// sum_g conj(s_g[y][x]) X_g[y][x].  GEMM M = (coil, y), N = x, K = samples,
+// split over sample ranges; partial images are summed in a fixed order
+// afterwards.
 //
-// Complex arithmetic on real MFMA: with A = Ar + i Ai and B = Br + i Bi, the
-// two K-slots of v_mfma_f32_32x32x2_f32 carry the real and imaginary parts:
-//   C_re += [Ar, -Ai] . [Br; Bi],   C_im += [Ai, Ar] . [Br; Bi],
-// so one complex multiply-add costs exactly the 8 real flops it contains.
+// Complex products on real MFMA (v_mfma_f32_32x32x2_f32): the two K-slots of
+// the instruction carry the real and imaginary parts, so with the A operand
+// [Ar, Ai] in slots (0, 1):
+//   C_re += [Ar, Ai] . [Br; -Bi],   C_im += [Ar, Ai] . [Bi; Br]
+// and a complex multiply-add costs exactly its 8 real flops.  Operands sit in
+// LDS as planes (Ar, Ai | Br, Bi, -Bi) with K contiguous, so every lane loads
+// four K values with one 16-byte read and no per-product select.
+//
+// Pipeline: two LDS stages; while the matrix cores consume stage s, global
+// loads for stage s+1 are in flight and its phase tiles are generated; one
+// barrier per K-step.
 #include "device.h"
 #include "internal.h"
+#include "phase.h"
 
 namespace mri {
 namespace {
 
-constexpr int kThreads = 256;            // 4 waves: 2 (rows) x 2 (cols)
-constexpr int kNT = 4;                   // 32-row MFMA tiles per wave
-constexpr int kChunkRows = 2 * kNT * 32; // rows per pass (256)
-constexpr int KC = kKStep;               // complex K values per stage
-constexpr int kLd = KC + 2;              // padded LDS row (complex); rows stay 16 B aligned
+constexpr int kThreads = 256;             // 4 waves: 2 (rows) x 2 (cols)
+constexpr int kNT = 4;                    // 32-row MFMA tiles per wave
+constexpr int kRows = 2 * kNT * 32;       // GEMM rows per pass (256)
+constexpr int KC = kKStep;                // complex K values per stage (8)
+constexpr int RS = KC + 4;                // LDS row stride in floats: conflict-free 16-byte reads
 
 __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
     int i = 0;
@@ -38,41 +46,59 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
     return i;
 }
 
-// One stage of MFMA work: rows of A (this wave's row tiles) times one 32-wide
-// column tile of B, over KC complex K values held in LDS as float2 rows.
-// lane layout of v_mfma_f32_32x32x2_f32: A[m][s] in lane m + 32 s, B[s][n] in
-// lane n + 32 s, so lanes 0-31 feed the real parts and 32-63 the imaginary.
-__device__ __forceinline__ void mfma_stage_f32(const float2* __restrict__ sa, const float2* __restrict__ sb,
-                                               int arow0, int bcol0, int lane, int nvalid_tiles,
+// One stage: this wave's kNT row tiles x one 32-wide column tile, KC complex K.
+// ap: A plane (re for lanes 0-31, im for 32-63) at this wave's first row;
+// bre/bim: B planes giving [Br; -Bi] and [Bi; Br] per lane half.
+__device__ __forceinline__ void mfma_stage_f32(const float* __restrict__ ap, const float* __restrict__ bre,
+                                               const float* __restrict__ bim, int nvalid,
                                                floatx16 (&acc_re)[kNT], floatx16 (&acc_im)[kNT]) {
-    const int h = lane >> 5, l32 = lane & 31;
-    const float4* bq_ptr = reinterpret_cast<const float4*>(sb + (bcol0 + l32) * kLd);
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 2) {
-        const float4 bq = bq_ptr[kk >> 1];
-        const float b0 = h ? bq.y : bq.x;
-        const float b1 = h ? bq.w : bq.z;
+    for (int kq = 0; kq < KC; kq += 4) {
+        const floatx4 br = *reinterpret_cast<const floatx4*>(bre + kq);
+        const floatx4 bi = *reinterpret_cast<const floatx4*>(bim + kq);
 #pragma unroll
         for (int t = 0; t < kNT; ++t) {
-            if (t < nvalid_tiles) {
-                const float4 aq = reinterpret_cast<const float4*>(sa + (arow0 + t * 32 + l32) * kLd)[kk >> 1];
-                const float are0 = h ? -aq.y : aq.x, aim0 = h ? aq.x : aq.y;
-                const float are1 = h ? -aq.w : aq.z, aim1 = h ? aq.z : aq.w;
-                acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(are0, b0, acc_re[t], 0, 0, 0);
-                acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim0, b0, acc_im[t], 0, 0, 0);
-                acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(are1, b1, acc_re[t], 0, 0, 0);
-                acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(aim1, b1, acc_im[t], 0, 0, 0);
+            if (t < nvalid) {
+                const floatx4 a = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], br[j], acc_re[t], 0, 0, 0);
+                    acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], bi[j], acc_im[t], 0, 0, 0);
+                }
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Forward: tile = (slice, coil, 64 samples); rows = every y (passes of 256).
+// Pre-pass of the forward: I[b][g][y][x] = s_g[y][x] x_b[y][x], rows padded to
+// a multiple of KC with zeros so the GEMM loads whole K-steps unguarded.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const NudftItem& it = tab.it[0];
+    const int64_t rowlen = ceil_div(it.nx, KC) * KC;
+    const int64_t per_coil = rowlen * it.ny;
+    const int64_t bg = i / per_coil;
+    const int64_t rem = i - bg * per_coil;
+    const int y = (int)(rem / rowlen), x = (int)(rem - (int64_t)y * rowlen);
+    const int g = (int)(bg % it.nc), b = (int)(bg / it.nc);
+    float2 v = make_float2(0.f, 0.f);
+    if (x < it.nx) {
+        const int64_t npix = (int64_t)it.nx * it.ny;
+        const int64_t p = (int64_t)y * it.nx + x;
+        v = cmul(it.smaps[b * it.smaps_bs + g * npix + p], it.img[b * npix + p]);
+    }
+    it.wimg[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Forward: tile = (slice, coil, 64 samples); rows = every y in passes of 256.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable tab) {
-    __shared__ __attribute__((aligned(16))) float2 sa[kChunkRows * kLd];
-    __shared__ __attribute__((aligned(16))) float2 sb[kFwdCols * kLd];
+    __shared__ __attribute__((aligned(16))) float sA[2][2][kRows][RS];     // stage, (re, im), row, k
+    __shared__ __attribute__((aligned(16))) float sB[2][3][kFwdCols][RS];  // stage, (re, im, -im), col, k
     __shared__ float2 red[2][kFwdCols];
 
     const int tile = xcd_remap(blockIdx.x, tab.total_tiles);
@@ -90,71 +116,116 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable ta
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
     const int64_t k0 = (int64_t)kb * kFwdCols;
-    const int64_t npix = (int64_t)nx * ny;
+    const int pitch = (int)ceil_div(nx, KC) * KC;
     const double* traj = it.traj + b * it.traj_bs;
-    const float2* sm = it.smaps + b * it.smaps_bs + (int64_t)g * npix;
-    const float2* im = it.img + (int64_t)b * npix;
+    const float2* wi = it.wimg + ((int64_t)b * nc + g) * ny * pitch;
     const int xh = nx / 2, yh = ny / 2;
 
-    // B-producer role: sample column pc, K pair pk.
-    const int pc = tid & 63, pk = (tid >> 6) * 2;
+    // B producer: sample column pc, K pair pj.  Ex[k][x0+j] = base(x0) * w_j.
+    const int pc = tid & 63, pj = (tid >> 6) * 2;
     const bool p_ok = k0 + pc < nk;
-    const double fxp = p_ok ? traj[2 * (k0 + pc)] * kInv2Pi : 0.0;
-    // Epilogue role: this lane's sample column.
+    const double fx4 = p_ok ? traj[2 * (k0 + pc)] * kQuarterTurnsPerRad : 0.0;
+    const float2 w0 = phase_neg(fx4, (double)pj);
+    const float2 w1 = phase_neg(fx4, (double)(pj + 1));
+    // Epilogue: this lane's sample column.
     const int64_t ke = k0 + wn * 32 + l32;
     const bool e_ok = ke < nk;
-    const double fye = e_ok ? traj[2 * ke + 1] * kInv2Pi : 0.0;
+    const double fy4 = e_ok ? traj[2 * ke + 1] * kQuarterTurnsPerRad : 0.0;
 
-    const int nsteps = (nx + KC - 1) / KC;
+    const int nsteps = pitch / KC;
     float2 dsum = make_float2(0.f, 0.f);
 
-    for (int y0 = 0; y0 < ny; y0 += kChunkRows) {
+    const float* ap0 = &sA[0][h][wm * (kNT * 32) + l32][0];
+    const float* bre0 = &sB[0][h ? 2 : 0][wn * 32 + l32][0];
+    const float* bim0 = &sB[0][h ? 0 : 1][wn * 32 + l32][0];
+    constexpr int kStageA = 2 * kRows * RS, kStageB = 3 * kFwdCols * RS;
+
+    for (int y0 = 0; y0 < ny; y0 += kRows) {
         const int wrow0 = y0 + wm * (kNT * 32);
         const int nvalid = wrow0 >= ny ? 0 : min(kNT, (ny - wrow0 + 31) / 32);
+        const int yrow = y0 + tid;
+        const bool row_ok = yrow < ny;
+        const float4* src = reinterpret_cast<const float4*>(wi + (int64_t)(row_ok ? yrow : 0) * pitch);
+        float4 pre[KC / 2];
+
+        auto load_a = [&](int s) {
+#pragma unroll
+            for (int j = 0; j < KC / 2; ++j)
+                pre[j] = row_ok ? src[s * (KC / 2) + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+        };
+        auto store_a = [&](int st) {
+            float* re = &sA[st][0][tid][0];
+            float* im = &sA[st][1][tid][0];
+#pragma unroll
+            for (int j = 0; j < KC / 4; ++j) {
+                *reinterpret_cast<float4*>(re + 4 * j) =
+                    make_float4(pre[2 * j].x, pre[2 * j].z, pre[2 * j + 1].x, pre[2 * j + 1].z);
+                *reinterpret_cast<float4*>(im + 4 * j) =
+                    make_float4(pre[2 * j].y, pre[2 * j].w, pre[2 * j + 1].y, pre[2 * j + 1].w);
+            }
+        };
+        auto store_b = [&](int st, int s) {
+            float2 e0 = make_float2(0.f, 0.f), e1 = e0;
+            if (p_ok) {
+                const float2 base = phase_neg(fx4, (double)(s * KC - xh));
+                e0 = cmul(base, w0);
+                e1 = cmul(base, w1);
+            }
+            *reinterpret_cast<float2*>(&sB[st][0][pc][pj]) = make_float2(e0.x, e1.x);
+            *reinterpret_cast<float2*>(&sB[st][1][pc][pj]) = make_float2(e0.y, e1.y);
+            *reinterpret_cast<float2*>(&sB[st][2][pc][pj]) = make_float2(-e0.y, -e1.y);
+        };
+
         floatx16 acc_re[kNT], acc_im[kNT];
 #pragma unroll
         for (int t = 0; t < kNT; ++t) {
             acc_re[t] = floatx16{0};
             acc_im[t] = floatx16{0};
         }
+        load_a(0);
+        store_a(0);
+        store_b(0, 0);
+        __syncthreads();
         for (int s = 0; s < nsteps; ++s) {
-            const int x0 = s * KC;
-            {   // A: I[y][x0 .. x0+KC) = s_g (.) x_b, one row per thread
-                const int y = y0 + tid;
-                float2 v[KC];
-#pragma unroll
-                for (int j = 0; j < KC; ++j) {
-                    const int x = x0 + j;
-                    v[j] = (y < ny && x < nx) ? cmul(sm[(int64_t)y * nx + x], im[(int64_t)y * nx + x])
-                                              : make_float2(0.f, 0.f);
-                }
-                float4* dst = reinterpret_cast<float4*>(sa + tid * kLd);
-#pragma unroll
-                for (int j = 0; j < KC; j += 2) dst[j >> 1] = make_float4(v[j].x, v[j].y, v[j + 1].x, v[j + 1].y);
+            const int cur = s & 1;
+            const bool more = s + 1 < nsteps;
+            if (more) load_a(s + 1);
+            mfma_stage_f32(ap0 + cur * kStageA, bre0 + cur * kStageB, bim0 + cur * kStageB, nvalid, acc_re, acc_im);
+            if (more) {
+                store_a(cur ^ 1);
+                store_b(cur ^ 1, s + 1);
             }
-            {   // B: Ex[k][x] for 64 samples x KC pixels
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int x = x0 + pk + j;
-                    sb[pc * kLd + pk + j] = (p_ok && x < nx) ? expi_neg(fxp, (double)(x - xh)) : make_float2(0.f, 0.f);
-                }
-            }
-            __syncthreads();
-            mfma_stage_f32(sa, sb, wm * (kNT * 32), wn * 32, lane, nvalid, acc_re, acc_im);
             __syncthreads();
         }
-        // Epilogue: sum over this pass's rows y of T[y][k] Ey[k][y].
+
+        // Epilogue: sum_y T[y][k] Ey[k][y] over this pass's rows.  Rows of a
+        // lane are ybase + 32 t + 8 q + r (r < 4); the phase is built as
+        // Ey(ybase) * E(32 t) * E(8 q) * E(r) from ten accurate factors.
         float2 part = make_float2(0.f, 0.f);
-        if (e_ok) {
+        if (e_ok && nvalid > 0) {
+            const int ybase = wrow0 + h * 4 - yh;
+            const float2 e0 = phase_neg(fy4, (double)ybase);
+            float2 f1[4], f8[4], f32[kNT];
+            f1[0] = f8[0] = f32[0] = make_float2(1.f, 0.f);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                f1[j] = phase_neg(fy4, (double)j);
+                f8[j] = phase_neg(fy4, (double)(8 * j));
+            }
+#pragma unroll
+            for (int j = 1; j < kNT; ++j) f32[j] = phase_neg(fy4, (double)(32 * j));
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
                 if (t < nvalid) {
+                    const float2 et = cmul(e0, f32[t]);
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int y = wrow0 + t * 32 + (i >> 2) * 8 + h * 4 + (i & 3);
-                        if (y < ny) {
-                            const float2 e = expi_neg(fye, (double)(y - yh));
-                            part = cadd(part, cmul(make_float2(acc_re[t][i], acc_im[t][i]), e));
+                    for (int q = 0; q < 4; ++q) {
+                        const float2 etq = cmul(et, f8[q]);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int i = q * 4 + r;
+                            const int y = wrow0 + t * 32 + q * 8 + h * 4 + r;
+                            if (y < ny) part = cadd(part, cmul(make_float2(acc_re[t][i], acc_im[t][i]), cmul(etq, f1[r])));
                         }
                     }
                 }
@@ -171,12 +242,13 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable ta
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: tile = (slice, split, 32 y rows, 64 x columns); rows of the GEMM
-// are (coil, y) for a group of 8 coils per pass.
+// Adjoint: tile = (slice, split, 32 y rows, 64 x columns); GEMM rows are
+// (coil, y) for a group of 8 coils per pass.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable tab) {
-    __shared__ __attribute__((aligned(16))) float2 sa[kChunkRows * kLd];
-    __shared__ __attribute__((aligned(16))) float2 sb[kAdjCols * kLd];
+    __shared__ __attribute__((aligned(16))) float sA[2][2][kRows][RS];     // stage, (re, im), (coil, y), k
+    __shared__ __attribute__((aligned(16))) float sB[2][3][kAdjCols][RS];  // stage, (re, im, -im), x, k
+    __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC];    // conj(Ey) for the next A
 
     const int tile = xcd_remap(blockIdx.x, tab.total_tiles);
     const NudftItem& it = tab.it[find_item(tab, tile)];
@@ -205,54 +277,104 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable ta
     const int nsteps = (int)ceil_div(kend - kbeg, KC);
 
     // Producer roles.
-    const int ayl = tid & 31, akj = tid >> 5;            // A: (y, k) pair
-    const int bxc = tid & 63, bkp = (tid >> 6) * 2;      // B: (x, k pair)
-    const int ya = y0 + ayl;
-    const int xbp = x0 + bxc;
-    // Epilogue role.
-    const int xe = x0 + wn * 32 + l32;
+    const int ey = tid & 31, ek = tid >> 5;              // E: (y, k)
+    const int bx = tid & 63, bk = (tid >> 6) * 2;        // B: (x, k pair)
+    const int ac = tid >> 5, ay = tid & 31;              // A: (coil, y)
+    const double yr = (double)(y0 + ey - yh);
+    const bool ey_ok = y0 + ey < ny;
+    const double xr = (double)(x0 + bx - xh);
+    const bool bx_ok = x0 + bx < nx;
+    const int xe = x0 + wn * 32 + l32;                   // epilogue column
 
-    float2 part[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) part[i] = make_float2(0.f, 0.f);
+    const float* ap0 = &sA[0][h][wm * (kNT * 32) + l32][0];
+    const float* bre0 = &sB[0][h ? 2 : 0][wn * 32 + l32][0];
+    const float* bim0 = &sB[0][h ? 0 : 1][wn * 32 + l32][0];
+    constexpr int kStageA = 2 * kRows * RS, kStageB = 3 * kAdjCols * RS;
 
+    const int ncgroups = (nc + kAdjCoilGroup - 1) / kAdjCoilGroup;
     for (int g0 = 0; g0 < nc; g0 += kAdjCoilGroup) {
         const int ncg = min(kAdjCoilGroup, nc - g0);
         const int nvalid = max(0, min(kNT, ncg - wm * kNT));
+        const bool a_ok = ac < ncg;
+        const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk;
+        float2 dreg[KC];
+
+        auto load_d = [&](int s) {
+            const int64_t kb0 = kbeg + (int64_t)s * KC;
+#pragma unroll
+            for (int j = 0; j < KC; ++j)
+                dreg[j] = (a_ok && kb0 + j < kend) ? drow[kb0 + j] : make_float2(0.f, 0.f);
+        };
+        auto gen_e = [&](int st, int s) {
+            const int64_t k = kbeg + (int64_t)s * KC + ek;
+            float2 e = make_float2(0.f, 0.f);
+            if (ey_ok && k < kend) e = phase_pos(traj[2 * k + 1] * kQuarterTurnsPerRad, yr);
+            sE[st][ey][ek] = e;
+        };
+        auto gen_b = [&](int st, int s) {
+            const int64_t k = kbeg + (int64_t)s * KC + bk;
+            float2 e0 = make_float2(0.f, 0.f), e1 = e0;
+            if (bx_ok && k < kend) e0 = phase_pos(traj[2 * k] * kQuarterTurnsPerRad, xr);
+            if (bx_ok && k + 1 < kend) e1 = phase_pos(traj[2 * k + 2] * kQuarterTurnsPerRad, xr);
+            *reinterpret_cast<float2*>(&sB[st][0][bx][bk]) = make_float2(e0.x, e1.x);
+            *reinterpret_cast<float2*>(&sB[st][1][bx][bk]) = make_float2(e0.y, e1.y);
+            *reinterpret_cast<float2*>(&sB[st][2][bx][bk]) = make_float2(-e0.y, -e1.y);
+        };
+        auto gen_a = [&](int st, int est) {
+            float wr[KC], wim[KC];
+#pragma unroll
+            for (int j = 0; j < KC; j += 2) {
+                const float4 e2 = *reinterpret_cast<const float4*>(&sE[est][ay][j]);
+                const float2 wa = cmul(dreg[j], make_float2(e2.x, e2.y));
+                const float2 wb = cmul(dreg[j + 1], make_float2(e2.z, e2.w));
+                wr[j] = wa.x;
+                wim[j] = wa.y;
+                wr[j + 1] = wb.x;
+                wim[j + 1] = wb.y;
+            }
+            float* re = &sA[st][0][ac * 32 + ay][0];
+            float* im = &sA[st][1][ac * 32 + ay][0];
+#pragma unroll
+            for (int j = 0; j < KC; j += 4) {
+                *reinterpret_cast<float4*>(re + j) = make_float4(wr[j], wr[j + 1], wr[j + 2], wr[j + 3]);
+                *reinterpret_cast<float4*>(im + j) = make_float4(wim[j], wim[j + 1], wim[j + 2], wim[j + 3]);
+            }
+        };
+
         floatx16 acc_re[kNT], acc_im[kNT];
 #pragma unroll
         for (int t = 0; t < kNT; ++t) {
             acc_re[t] = floatx16{0};
             acc_im[t] = floatx16{0};
         }
+        // Prologue: E(0), d(0) -> A(0), B(0); E(1), d(1) ready for the loop.
+        gen_e(0, 0);
+        load_d(0);
+        __syncthreads();
+        gen_a(0, 0);
+        gen_b(0, 0);
+        if (nsteps > 1) {
+            gen_e(1, 1);
+            load_d(1);
+        }
+        __syncthreads();
         for (int s = 0; s < nsteps; ++s) {
-            const int64_t kb0 = kbeg + (int64_t)s * KC;
-            {   // A: W[(c, y)][k] = y[g0+c][k] conj(Ey[k][y])
-                const int64_t k = kb0 + akj;
-                const bool ok = k < kend && ya < ny;
-                float2 cey = make_float2(0.f, 0.f);
-                if (ok) cey = expi_pos(traj[2 * k + 1] * kInv2Pi, (double)(ya - yh));
-#pragma unroll
-                for (int c = 0; c < kAdjCoilGroup; ++c) {
-                    float2 w = make_float2(0.f, 0.f);
-                    if (ok && c < ncg) w = cmul(dat[(int64_t)(g0 + c) * nk + k], cey);
-                    sa[(c * 32 + ayl) * kLd + akj] = w;
-                }
+            const int cur = s & 1;
+            mfma_stage_f32(ap0 + cur * kStageA, bre0 + cur * kStageB, bim0 + cur * kStageB, nvalid, acc_re, acc_im);
+            if (s + 1 < nsteps) {
+                gen_a(cur ^ 1, cur ^ 1);              // W(s+1) from d(s+1) and E(s+1)
+                if (s + 2 < nsteps) load_d(s + 2);
+                gen_b(cur ^ 1, s + 1);
+                if (s + 2 < nsteps) gen_e(cur, s + 2);
             }
-            {   // B: conj(Ex[k][x]) for 64 x
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int64_t k = kb0 + bkp + j;
-                    sb[bxc * kLd + bkp + j] = (k < kend && xbp < nx)
-                                                  ? expi_pos(traj[2 * k] * kInv2Pi, (double)(xbp - xh))
-                                                  : make_float2(0.f, 0.f);
-                }
-            }
-            __syncthreads();
-            mfma_stage_f32(sa, sb, wm * (kNT * 32), wn * 32, lane, nvalid, acc_re, acc_im);
             __syncthreads();
         }
-        // Coil combine of this group: part[y] += conj(s_g[y][x]) X_g[y][x].
+        // Coil combine of this group: sum_g conj(s_g[y][x]) X_g[y][x], then the
+        // two row-waves (coils 0-3 and 4-7 of the group) meet through LDS and
+        // the group's partial image is written for the fixed-order reduction.
+        float2 part[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) part[i] = make_float2(0.f, 0.f);
         if (xe < nx) {
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
@@ -269,20 +391,20 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable ta
                 }
             }
         }
-    }
-    // Combine the two row-waves (coils 0-3 and 4-7 of each group) through LDS.
-    float2* red = sa;   // reuse: 2 (wn) x 16 x 64 complex
-    if (wm == 1) {
+        float2* red = reinterpret_cast<float2*>(&sA[0][0][0][0]);   // 2 (wn) x 16 x 64 complex
+        if (wm == 1) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) red[(wn * 16 + i) * 64 + lane] = part[i];
-    }
-    __syncthreads();
-    if (wm == 0 && xe < nx) {
-        float2* out = it.part + ((int64_t)sp * it.nb + b) * npix;
+            for (int i = 0; i < 16; ++i) red[(wn * 16 + i) * 64 + lane] = part[i];
+        }
+        __syncthreads();
+        if (wm == 0 && xe < nx) {
+            const int plane = sp * ncgroups + g0 / kAdjCoilGroup;
+            float2* out = it.part + ((int64_t)plane * it.nb + b) * npix;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int y = y0 + (i >> 2) * 8 + h * 4 + (i & 3);
-            if (y < ny) out[(int64_t)y * nx + xe] = cadd(part[i], red[(wn * 16 + i) * 64 + lane]);
+            for (int i = 0; i < 16; ++i) {
+                const int y = y0 + (i >> 2) * 8 + h * 4 + (i & 3);
+                if (y < ny) out[(int64_t)y * nx + xe] = cadd(part[i], red[(wn * 16 + i) * 64 + lane]);
+            }
         }
     }
 }
@@ -292,6 +414,14 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable ta
 int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb) {
     (void)nx; (void)ny;
     return (int64_t)nb * nc * ceil_div(nk, kFwdCols);
+}
+
+int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb) {
+    return (int64_t)nb * nc * ny * (ceil_div(nx, KC) * KC);
+}
+
+int adj_partial_planes(int nc, int ksplit) {
+    return ksplit * (int)ceil_div(nc, kAdjCoilGroup);
 }
 
 int64_t adj_tiles_per_split(int nx, int ny, int nb) {
@@ -314,6 +444,14 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
     s = ceil_div(nk, per);
     *ksplit = (int32_t)s;
     *kper = (int32_t)per;
+}
+
+hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s) {
+    const NudftItem& it = t.it[0];
+    const int64_t total = fwd_wimg_elems(it.nx, it.ny, it.nc, it.nb);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, t, total);
+    return hipGetLastError();
 }
 
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s) {
