@@ -42,7 +42,7 @@ int check_shape(const mri_shape* s) {
 
 int check_precision(int p) {
     if (p == MRI_FP32) return MRI_OK;
-    if (p == MRI_BF16X3) return MRI_ENOTSUP;
+    if (p == MRI_BF16X3) return MRI_OK;
     return MRI_EINVAL;
 }
 

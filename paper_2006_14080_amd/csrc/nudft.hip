@@ -46,29 +46,173 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
     return i;
 }
 
-// One stage: this wave's kNT row tiles x one 32-wide column tile, KC complex K.
-// ap: A plane (re for lanes 0-31, im for 32-63) at this wave's first row;
-// bre/bim: B planes giving [Br; -Bi] and [Bi; Br] per lane half.
-__device__ __forceinline__ void mfma_stage_f32(const float* __restrict__ ap, const float* __restrict__ bre,
-                                               const float* __restrict__ bim, int nvalid,
-                                               floatx16 (&acc_re)[kNT], floatx16 (&acc_im)[kNT]) {
+// ---------------------------------------------------------------------------
+// Operand policies.  A stage holds kRows GEMM rows x KC complex K values of
+// the A operand; B holds 64 columns of the B operand in the two forms
+// (Br, -Bi) and (Bi, Br) that produce the real and imaginary accumulators.
+//   store_a(stage, row, v[KC])        one row of A, K values 0..KC-1
+//   store_b(stage, col, kp, e0, e1)   B column col, K values kp, kp+1
+//   mma(a, b, arow0, bcol0, lane, nvalid, acc_re, acc_im)
+// ---------------------------------------------------------------------------
+
+// FP32: v_mfma_f32_32x32x2_f32, K-slot 0 = real part, slot 1 = imaginary.
+// LDS planes with K contiguous: A (Ar, Ai); B (Br, Bi, -Bi).  Lanes 0-31 read
+// plane Ar / Br / Bi, lanes 32-63 read Ai / -Bi / Br, four K values per read.
+struct PolF32 {
+    static constexpr int kABytes = 2 * kRows * RS * 4;
+    static constexpr int kBBytes = 3 * 64 * RS * 4;
+
+    __device__ __forceinline__ static void store_a(char* st, int row, const float2 (&v)[KC]) {
+        float* re = reinterpret_cast<float*>(st) + row * RS;
+        float* im = re + kRows * RS;
 #pragma unroll
-    for (int kq = 0; kq < KC; kq += 4) {
-        const floatx4 br = *reinterpret_cast<const floatx4*>(bre + kq);
-        const floatx4 bi = *reinterpret_cast<const floatx4*>(bim + kq);
+        for (int j = 0; j < KC; j += 4) {
+            *reinterpret_cast<float4*>(re + j) = make_float4(v[j].x, v[j + 1].x, v[j + 2].x, v[j + 3].x);
+            *reinterpret_cast<float4*>(im + j) = make_float4(v[j].y, v[j + 1].y, v[j + 2].y, v[j + 3].y);
+        }
+    }
+    __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
+        float* p = reinterpret_cast<float*>(st) + col * RS + kp;
+        *reinterpret_cast<float2*>(p) = make_float2(e0.x, e1.x);
+        *reinterpret_cast<float2*>(p + 64 * RS) = make_float2(e0.y, e1.y);
+        *reinterpret_cast<float2*>(p + 128 * RS) = make_float2(-e0.y, -e1.y);
+    }
+    __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
+                                               int nvalid, floatx16 (&acc_re)[kNT], floatx16 (&acc_im)[kNT]) {
+        const int h = lane >> 5, l32 = lane & 31;
+        const float* ap = reinterpret_cast<const float*>(a) + (h * kRows + arow0 + l32) * RS;
+        const float* bre = reinterpret_cast<const float*>(b) + ((h ? 2 : 0) * 64 + bcol0 + l32) * RS;
+        const float* bim = reinterpret_cast<const float*>(b) + ((h ? 0 : 1) * 64 + bcol0 + l32) * RS;
 #pragma unroll
-        for (int t = 0; t < kNT; ++t) {
-            if (t < nvalid) {
-                const floatx4 a = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
+        for (int kq = 0; kq < KC; kq += 4) {
+            const floatx4 br = *reinterpret_cast<const floatx4*>(bre + kq);
+            const floatx4 bi = *reinterpret_cast<const floatx4*>(bim + kq);
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], br[j], acc_re[t], 0, 0, 0);
-                    acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], bi[j], acc_im[t], 0, 0, 0);
+            for (int t = 0; t < kNT; ++t) {
+                if (t < nvalid) {
+                    const floatx4 av = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], br[j], acc_re[t], 0, 0, 0);
+                        acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bi[j], acc_im[t], 0, 0, 0);
+                    }
                 }
             }
         }
     }
-}
+};
+
+// Split-BF16 (Sec. II-A "decomposition and accumulation"): each FP32 value
+// a = hi + lo with hi = bf16(a), lo = bf16(a - hi) (round to nearest even);
+// a real product a b is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b, FP32
+// accumulation.  v_mfma_f32_32x32x16_bf16 takes 8 K-slots per lane half; the
+// six products of a complex K value for one accumulator occupy six slots:
+//   A    : [ArH, ArH, ArL, AiH, AiH, AiL]
+//   B_re : [BrH, BrL, BrH, -BiH, -BiL, -BiH]   -> Ar Br - Ai Bi
+//   B_im : [BiH, BiL, BiH, BrH, BrL, BrH]      -> Ar Bi + Ai Br
+// Lane half h takes complex K values 4h..4h+3 (24 slots = 3 instructions),
+// so 8 complex K values cost 3 MFMAs per accumulator with no idle slot.
+// LDS keeps every 16-byte operand chunk ready: A [h][m][row], B [var][h][m][col].
+struct PolBF16 {
+    static constexpr int kABytes = 2 * 3 * kRows * 16;
+    static constexpr int kBBytes = 2 * 2 * 3 * 64 * 16;
+
+    struct Sp {
+        __bf16 h, l;
+    };
+    __device__ __forceinline__ static Sp split(float a) {
+        Sp s;
+        s.h = static_cast<__bf16>(a);
+        s.l = static_cast<__bf16>(a - static_cast<float>(s.h));
+        return s;
+    }
+    // slot value of term t (0..5) for the A operand
+    __device__ __forceinline__ static __bf16 a_term(int t, Sp r, Sp i) {
+        return t == 0 || t == 1 ? r.h : t == 2 ? r.l : t == 5 ? i.l : i.h;
+    }
+    __device__ __forceinline__ static __bf16 bre_term(int t, Sp r, Sp i) {
+        return t == 0 || t == 2 ? r.h : t == 1 ? r.l : t == 4 ? -i.l : -i.h;
+    }
+    __device__ __forceinline__ static __bf16 bim_term(int t, Sp r, Sp i) {
+        return t == 0 || t == 2 ? i.h : t == 1 ? i.l : t == 4 ? r.l : r.h;
+    }
+
+    __device__ __forceinline__ static void store_a(char* st, int row, const float2 (&v)[KC]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            Sp r[4], i[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                r[q] = split(v[4 * h + q].x);
+                i[q] = split(v[4 * h + q].y);
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                bf16x8 c;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int slot = 8 * m + j, q = slot / 6, t = slot % 6;
+                    c[j] = a_term(t, r[q], i[q]);
+                }
+                *reinterpret_cast<bf16x8*>(st + ((h * 3 + m) * kRows + row) * 16) = c;
+            }
+        }
+    }
+    __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
+        const int h = kp >> 2;
+        const Sp r0 = split(e0.x), i0 = split(e0.y), r1 = split(e1.x), i1 = split(e1.y);
+#pragma unroll
+        for (int var = 0; var < 2; ++var) {
+            __bf16 sl[12];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                sl[t] = var == 0 ? bre_term(t, r0, i0) : bim_term(t, r0, i0);
+                sl[6 + t] = var == 0 ? bre_term(t, r1, i1) : bim_term(t, r1, i1);
+            }
+            char* base = st + (((var * 2 + h) * 3) * 64 + col) * 16;
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            if ((kp & 3) == 0) {
+                // slots 0..11: chunk 0 whole, first half of chunk 1
+                bf16x8 c0;
+                bf16x4 c1;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) c0[j] = sl[j];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) c1[j] = sl[8 + j];
+                *reinterpret_cast<bf16x8*>(base) = c0;
+                *reinterpret_cast<bf16x4*>(base + 64 * 16) = c1;
+            } else {
+                // slots 12..23: second half of chunk 1, chunk 2 whole
+                bf16x4 c1;
+                bf16x8 c2;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) c1[j] = sl[j];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) c2[j] = sl[4 + j];
+                *reinterpret_cast<bf16x4*>(base + 64 * 16 + 8) = c1;
+                *reinterpret_cast<bf16x8*>(base + 2 * 64 * 16) = c2;
+            }
+        }
+    }
+    __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
+                                               int nvalid, floatx16 (&acc_re)[kNT], floatx16 (&acc_im)[kNT]) {
+        const int h = lane >> 5, l32 = lane & 31;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const bf16x8 br = *reinterpret_cast<const bf16x8*>(b + (((0 * 2 + h) * 3 + m) * 64 + bcol0 + l32) * 16);
+            const bf16x8 bi = *reinterpret_cast<const bf16x8*>(b + (((1 * 2 + h) * 3 + m) * 64 + bcol0 + l32) * 16);
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) {
+                if (t < nvalid) {
+                    const bf16x8 av =
+                        *reinterpret_cast<const bf16x8*>(a + ((h * 3 + m) * kRows + arow0 + t * 32 + l32) * 16);
+                    acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, br, acc_re[t], 0, 0, 0);
+                    acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bi, acc_im[t], 0, 0, 0);
+                }
+            }
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Pre-pass of the forward: I[b][g][y][x] = s_g[y][x] x_b[y][x], rows padded to
@@ -96,10 +240,12 @@ __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab, int64
 // ---------------------------------------------------------------------------
 // Forward: tile = (slice, coil, 64 samples); rows = every y in passes of 256.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable tab) {
-    __shared__ __attribute__((aligned(16))) float sA[2][2][kRows][RS];     // stage, (re, im), row, k
-    __shared__ __attribute__((aligned(16))) float sB[2][3][kFwdCols][RS];  // stage, (re, im, -im), col, k
+template <class P>
+__global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + P::kBBytes)];
     __shared__ float2 red[2][kFwdCols];
+    char* const sA0 = smem;
+    char* const sB0 = smem + 2 * P::kABytes;
 
     const int tile = xcd_remap(blockIdx.x, tab.total_tiles);
     const NudftItem& it = tab.it[find_item(tab, tile)];
@@ -135,11 +281,6 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable ta
     const int nsteps = pitch / KC;
     float2 dsum = make_float2(0.f, 0.f);
 
-    const float* ap0 = &sA[0][h][wm * (kNT * 32) + l32][0];
-    const float* bre0 = &sB[0][h ? 2 : 0][wn * 32 + l32][0];
-    const float* bim0 = &sB[0][h ? 0 : 1][wn * 32 + l32][0];
-    constexpr int kStageA = 2 * kRows * RS, kStageB = 3 * kFwdCols * RS;
-
     for (int y0 = 0; y0 < ny; y0 += kRows) {
         const int wrow0 = y0 + wm * (kNT * 32);
         const int nvalid = wrow0 >= ny ? 0 : min(kNT, (ny - wrow0 + 31) / 32);
@@ -154,15 +295,13 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable ta
                 pre[j] = row_ok ? src[s * (KC / 2) + j] : make_float4(0.f, 0.f, 0.f, 0.f);
         };
         auto store_a = [&](int st) {
-            float* re = &sA[st][0][tid][0];
-            float* im = &sA[st][1][tid][0];
+            float2 v[KC];
 #pragma unroll
-            for (int j = 0; j < KC / 4; ++j) {
-                *reinterpret_cast<float4*>(re + 4 * j) =
-                    make_float4(pre[2 * j].x, pre[2 * j].z, pre[2 * j + 1].x, pre[2 * j + 1].z);
-                *reinterpret_cast<float4*>(im + 4 * j) =
-                    make_float4(pre[2 * j].y, pre[2 * j].w, pre[2 * j + 1].y, pre[2 * j + 1].w);
+            for (int j = 0; j < KC / 2; ++j) {
+                v[2 * j] = make_float2(pre[j].x, pre[j].y);
+                v[2 * j + 1] = make_float2(pre[j].z, pre[j].w);
             }
+            P::store_a(sA0 + st * P::kABytes, tid, v);
         };
         auto store_b = [&](int st, int s) {
             float2 e0 = make_float2(0.f, 0.f), e1 = e0;
@@ -171,9 +310,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable ta
                 e0 = cmul(base, w0);
                 e1 = cmul(base, w1);
             }
-            *reinterpret_cast<float2*>(&sB[st][0][pc][pj]) = make_float2(e0.x, e1.x);
-            *reinterpret_cast<float2*>(&sB[st][1][pc][pj]) = make_float2(e0.y, e1.y);
-            *reinterpret_cast<float2*>(&sB[st][2][pc][pj]) = make_float2(-e0.y, -e1.y);
+            P::store_b(sB0 + st * P::kBBytes, pc, pj, e0, e1);
         };
 
         floatx16 acc_re[kNT], acc_im[kNT];
@@ -190,7 +327,8 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable ta
             const int cur = s & 1;
             const bool more = s + 1 < nsteps;
             if (more) load_a(s + 1);
-            mfma_stage_f32(ap0 + cur * kStageA, bre0 + cur * kStageB, bim0 + cur * kStageB, nvalid, acc_re, acc_im);
+            P::mma(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (kNT * 32), wn * 32, lane, nvalid,
+                   acc_re, acc_im);
             if (more) {
                 store_a(cur ^ 1);
                 store_b(cur ^ 1, s + 1);
@@ -245,10 +383,12 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd_f32(const NudftTable ta
 // Adjoint: tile = (slice, split, 32 y rows, 64 x columns); GEMM rows are
 // (coil, y) for a group of 8 coils per pass.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable tab) {
-    __shared__ __attribute__((aligned(16))) float sA[2][2][kRows][RS];     // stage, (re, im), (coil, y), k
-    __shared__ __attribute__((aligned(16))) float sB[2][3][kAdjCols][RS];  // stage, (re, im, -im), x, k
+template <class P>
+__global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
+    __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + P::kBBytes)];
     __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC];    // conj(Ey) for the next A
+    char* const sA0 = smem;
+    char* const sB0 = smem + 2 * P::kABytes;
 
     const int tile = xcd_remap(blockIdx.x, tab.total_tiles);
     const NudftItem& it = tab.it[find_item(tab, tile)];
@@ -286,11 +426,6 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable ta
     const bool bx_ok = x0 + bx < nx;
     const int xe = x0 + wn * 32 + l32;                   // epilogue column
 
-    const float* ap0 = &sA[0][h][wm * (kNT * 32) + l32][0];
-    const float* bre0 = &sB[0][h ? 2 : 0][wn * 32 + l32][0];
-    const float* bim0 = &sB[0][h ? 0 : 1][wn * 32 + l32][0];
-    constexpr int kStageA = 2 * kRows * RS, kStageB = 3 * kAdjCols * RS;
-
     const int ncgroups = (nc + kAdjCoilGroup - 1) / kAdjCoilGroup;
     for (int g0 = 0; g0 < nc; g0 += kAdjCoilGroup) {
         const int ncg = min(kAdjCoilGroup, nc - g0);
@@ -316,29 +451,17 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable ta
             float2 e0 = make_float2(0.f, 0.f), e1 = e0;
             if (bx_ok && k < kend) e0 = phase_pos(traj[2 * k] * kQuarterTurnsPerRad, xr);
             if (bx_ok && k + 1 < kend) e1 = phase_pos(traj[2 * k + 2] * kQuarterTurnsPerRad, xr);
-            *reinterpret_cast<float2*>(&sB[st][0][bx][bk]) = make_float2(e0.x, e1.x);
-            *reinterpret_cast<float2*>(&sB[st][1][bx][bk]) = make_float2(e0.y, e1.y);
-            *reinterpret_cast<float2*>(&sB[st][2][bx][bk]) = make_float2(-e0.y, -e1.y);
+            P::store_b(sB0 + st * P::kBBytes, bx, bk, e0, e1);
         };
         auto gen_a = [&](int st, int est) {
-            float wr[KC], wim[KC];
+            float2 w[KC];
 #pragma unroll
             for (int j = 0; j < KC; j += 2) {
                 const float4 e2 = *reinterpret_cast<const float4*>(&sE[est][ay][j]);
-                const float2 wa = cmul(dreg[j], make_float2(e2.x, e2.y));
-                const float2 wb = cmul(dreg[j + 1], make_float2(e2.z, e2.w));
-                wr[j] = wa.x;
-                wim[j] = wa.y;
-                wr[j + 1] = wb.x;
-                wim[j + 1] = wb.y;
+                w[j] = cmul(dreg[j], make_float2(e2.x, e2.y));
+                w[j + 1] = cmul(dreg[j + 1], make_float2(e2.z, e2.w));
             }
-            float* re = &sA[st][0][ac * 32 + ay][0];
-            float* im = &sA[st][1][ac * 32 + ay][0];
-#pragma unroll
-            for (int j = 0; j < KC; j += 4) {
-                *reinterpret_cast<float4*>(re + j) = make_float4(wr[j], wr[j + 1], wr[j + 2], wr[j + 3]);
-                *reinterpret_cast<float4*>(im + j) = make_float4(wim[j], wim[j + 1], wim[j + 2], wim[j + 3]);
-            }
+            P::store_a(sA0 + st * P::kABytes, ac * 32 + ay, w);
         };
 
         floatx16 acc_re[kNT], acc_im[kNT];
@@ -360,7 +483,8 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable ta
         __syncthreads();
         for (int s = 0; s < nsteps; ++s) {
             const int cur = s & 1;
-            mfma_stage_f32(ap0 + cur * kStageA, bre0 + cur * kStageB, bim0 + cur * kStageB, nvalid, acc_re, acc_im);
+            P::mma(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (kNT * 32), wn * 32, lane, nvalid,
+                   acc_re, acc_im);
             if (s + 1 < nsteps) {
                 gen_a(cur ^ 1, cur ^ 1);              // W(s+1) from d(s+1) and E(s+1)
                 if (s + 2 < nsteps) load_d(s + 2);
@@ -391,7 +515,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj_f32(const NudftTable ta
                 }
             }
         }
-        float2* red = reinterpret_cast<float2*>(&sA[0][0][0][0]);   // 2 (wn) x 16 x 64 complex
+        float2* red = reinterpret_cast<float2*>(smem);   // 2 (wn) x 16 x 64 complex
         if (wm == 1) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) red[(wn * 16 + i) * 64 + lane] = part[i];
@@ -456,15 +580,19 @@ hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s) {
 
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s) {
     if (t.total_tiles <= 0) return hipSuccess;
-    (void)precision;
-    hipLaunchKernelGGL(nudft_fwd_f32, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
+    if (precision == MRI_BF16X3)
+        hipLaunchKernelGGL(nudft_fwd<PolBF16>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
+    else
+        hipLaunchKernelGGL(nudft_fwd<PolF32>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
     return hipGetLastError();
 }
 
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s) {
     if (t.total_tiles <= 0) return hipSuccess;
-    (void)precision;
-    hipLaunchKernelGGL(nudft_adj_f32, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
+    if (precision == MRI_BF16X3)
+        hipLaunchKernelGGL(nudft_adj<PolBF16>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
+    else
+        hipLaunchKernelGGL(nudft_adj<PolF32>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
     return hipGetLastError();
 }
 

@@ -40,11 +40,13 @@ def _oracle(p, data, b, lam, beta, na, nc, **kw):
     return oadmm.admm(data[b], p.smaps, p.traj, lam, beta, na, nc, **kw)
 
 
-def test_admm32_full_counts():
+@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3])
+def test_admm32_full_counts(prec):
+    # FP32: the plain 32x32 workload; BF16X3: its split-BF16 precision form.
     wl = synth.ADMM32
     p = synth.make_problem(wl)
     data = _data(p)
-    img, st = _solve(p, data, mri.AdmmParams(wl.lam, wl.beta, wl.admm_iters, wl.cg_iters))
+    img, st = _solve(p, data, mri.AdmmParams(wl.lam, wl.beta, wl.admm_iters, wl.cg_iters, precision=prec))
     ref = _oracle(p, data, 0, wl.lam, wl.beta, wl.admm_iters, wl.cg_iters)
     assert st[0]["status"] == 0
     assert st[0]["admm_iters"] == ref.admm_iters and st[0]["cg_steps"] == ref.cg_steps
@@ -101,13 +103,14 @@ def test_tolerances_stop_on_device():
     assert nrmse(img[0], ref.image) <= NRMSE
 
 
-def test_admm256_shape_reduced_counts():
+@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3])
+def test_admm256_shape_reduced_counts(prec):
     # The 256x256, 8-coil, 64x512-sample launch configuration of the benchmark,
     # with 2 ADMM x 2 CG steps so the oracle finishes in seconds.
     wl = synth.ADMM256
     p = synth.make_problem(wl)
     data = _data(p)
-    img, st = _solve(p, data, mri.AdmmParams(wl.lam, wl.beta, 2, 2))
+    img, st = _solve(p, data, mri.AdmmParams(wl.lam, wl.beta, 2, 2, precision=prec))
     ref = _oracle(p, data, 0, wl.lam, wl.beta, 2, 2)
     assert st[0]["admm_iters"] == 2 and st[0]["cg_steps"] == 4
     assert nrmse(img[0], ref.image) <= NRMSE
