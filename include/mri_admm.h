@@ -91,7 +91,8 @@ enum { MRI_OP_FORWARD = 0, MRI_OP_ADJOINT = 1, MRI_OP_ADMM = 2 };
  *   x [B][ny][nx], smaps, traj as above, y [B][nc][nk] (written).
  *   precision: MRI_FP32 or MRI_BF16X3.
  *   ws/ws_bytes: workspace of at least mri_workspace_bytes(shape,
- *   MRI_OP_FORWARD, NULL) bytes (may be NULL when that is 0).
+ *   MRI_OP_FORWARD, NULL) bytes; it receives the coil-weighted images
+ *   s (.) x (rows padded to a multiple of 8 pixels).
  * Errors: MRI_EINVAL, MRI_ENOTSUP, MRI_ENOMEM, MRI_EHIP.
  */
 int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps,
