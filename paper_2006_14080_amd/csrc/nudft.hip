@@ -83,19 +83,22 @@ struct PolF32 {
         const float* ap = reinterpret_cast<const float*>(a) + (h * kRows + arow0 + l32) * RS;
         const float* bre = reinterpret_cast<const float*>(b) + ((h ? 2 : 0) * 64 + bcol0 + l32) * RS;
         const float* bim = reinterpret_cast<const float*>(b) + ((h ? 0 : 1) * 64 + bcol0 + l32) * RS;
+        // Row tiles past the valid range hold zeros, so a wave with any live
+        // tile runs all of them (branch-free); a wave with none skips the stage.
+        if (__builtin_amdgcn_readfirstlane(nvalid) == 0) return;
 #pragma unroll
         for (int kq = 0; kq < KC; kq += 4) {
             const floatx4 br = *reinterpret_cast<const floatx4*>(bre + kq);
             const floatx4 bi = *reinterpret_cast<const floatx4*>(bim + kq);
+            floatx4 av[kNT];
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) {
-                if (t < nvalid) {
-                    const floatx4 av = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
+            for (int t = 0; t < kNT; ++t) av[t] = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], br[j], acc_re[t], 0, 0, 0);
-                        acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bi[j], acc_im[t], 0, 0, 0);
-                    }
+            for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                for (int t = 0; t < kNT; ++t) {
+                    acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t][j], br[j], acc_re[t], 0, 0, 0);
+                    acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t][j], bi[j], acc_im[t], 0, 0, 0);
                 }
             }
         }
@@ -197,18 +200,21 @@ struct PolBF16 {
     __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
                                                int nvalid, floatx16 (&acc_re)[kNT], floatx16 (&acc_im)[kNT]) {
         const int h = lane >> 5, l32 = lane & 31;
+        const char* bre = b + ((h * 3) * 64 + bcol0 + l32) * 16;
+        const char* bim = b + (((2 + h) * 3) * 64 + bcol0 + l32) * 16;
+        const char* ap = a + ((h * 3) * kRows + arow0 + l32) * 16;
+        if (__builtin_amdgcn_readfirstlane(nvalid) == 0) return;   // see PolF32::mma
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const bf16x8 br = *reinterpret_cast<const bf16x8*>(b + (((0 * 2 + h) * 3 + m) * 64 + bcol0 + l32) * 16);
-            const bf16x8 bi = *reinterpret_cast<const bf16x8*>(b + (((1 * 2 + h) * 3 + m) * 64 + bcol0 + l32) * 16);
+            const bf16x8 br = *reinterpret_cast<const bf16x8*>(bre + m * 64 * 16);
+            const bf16x8 bi = *reinterpret_cast<const bf16x8*>(bim + m * 64 * 16);
+            bf16x8 av[kNT];
+#pragma unroll
+            for (int t = 0; t < kNT; ++t) av[t] = *reinterpret_cast<const bf16x8*>(ap + (m * kRows + t * 32) * 16);
 #pragma unroll
             for (int t = 0; t < kNT; ++t) {
-                if (t < nvalid) {
-                    const bf16x8 av =
-                        *reinterpret_cast<const bf16x8*>(a + ((h * 3 + m) * kRows + arow0 + t * 32 + l32) * 16);
-                    acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, br, acc_re[t], 0, 0, 0);
-                    acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bi, acc_im[t], 0, 0, 0);
-                }
+                acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[t], br, acc_re[t], 0, 0, 0);
+                acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[t], bi, acc_im[t], 0, 0, 0);
             }
         }
     }
@@ -259,7 +265,8 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
     const int b = local / nc;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
     const int64_t k0 = (int64_t)kb * kFwdCols;
     const int pitch = (int)ceil_div(nx, KC) * KC;
@@ -286,20 +293,21 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         const int nvalid = wrow0 >= ny ? 0 : min(kNT, (ny - wrow0 + 31) / 32);
         const int yrow = y0 + tid;
         const bool row_ok = yrow < ny;
-        const float4* src = reinterpret_cast<const float4*>(wi + (int64_t)(row_ok ? yrow : 0) * pitch);
+        // rows past ny load row ny-1 (always in bounds) and are zeroed when staged
+        const float4* src = reinterpret_cast<const float4*>(wi + (int64_t)min(yrow, ny - 1) * pitch);
+        const float rmask = row_ok ? 1.0f : 0.0f;
         float4 pre[KC / 2];
 
         auto load_a = [&](int s) {
 #pragma unroll
-            for (int j = 0; j < KC / 2; ++j)
-                pre[j] = row_ok ? src[s * (KC / 2) + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+            for (int j = 0; j < KC / 2; ++j) pre[j] = src[s * (KC / 2) + j];
         };
         auto store_a = [&](int st) {
             float2 v[KC];
 #pragma unroll
             for (int j = 0; j < KC / 2; ++j) {
-                v[2 * j] = make_float2(pre[j].x, pre[j].y);
-                v[2 * j + 1] = make_float2(pre[j].z, pre[j].w);
+                v[2 * j] = make_float2(pre[j].x * rmask, pre[j].y * rmask);
+                v[2 * j + 1] = make_float2(pre[j].z * rmask, pre[j].w * rmask);
             }
             P::store_a(sA0 + st * P::kABytes, tid, v);
         };
@@ -386,7 +394,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
 template <class P>
 __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + P::kBBytes)];
-    __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC];    // conj(Ey) for the next A
+    __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC + 2];   // conj(Ey) for the next A (padded rows)
     char* const sA0 = smem;
     char* const sB0 = smem + 2 * P::kABytes;
 
@@ -404,7 +412,8 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     const int b = local / it.ksplit;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
     const int x0 = xb * kAdjCols, y0 = yb * kAdjRows;
     const int64_t npix = (int64_t)nx * ny;
@@ -434,32 +443,45 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
         const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk;
         float2 dreg[KC];
 
+        // Loads are unconditional from clamped (in-bounds) indices; samples past
+        // the split end are masked when staged, so no load sits in a branch.
         auto load_d = [&](int s) {
             const int64_t kb0 = kbeg + (int64_t)s * KC;
 #pragma unroll
-            for (int j = 0; j < KC; ++j)
-                dreg[j] = (a_ok && kb0 + j < kend) ? drow[kb0 + j] : make_float2(0.f, 0.f);
+            for (int j = 0; j < KC; ++j) dreg[j] = drow[min(kb0 + j, kend - 1)];
+        };
+        // Trajectory values are prefetched one step ahead of their use:
+        // tfx0/tfx1 for the next B stage, tfy for the E tile after that.
+        double tfx0, tfx1, tfy;
+        auto load_fx = [&](int s) {
+            const int64_t k = kbeg + (int64_t)s * KC + bk;
+            tfx0 = traj[2 * min(k, kend - 1)];
+            tfx1 = traj[2 * min(k + 1, kend - 1)];
+        };
+        auto load_fy = [&](int s) {
+            tfy = traj[2 * min(kbeg + (int64_t)s * KC + ek, kend - 1) + 1];
         };
         auto gen_e = [&](int st, int s) {
             const int64_t k = kbeg + (int64_t)s * KC + ek;
-            float2 e = make_float2(0.f, 0.f);
-            if (ey_ok && k < kend) e = phase_pos(traj[2 * k + 1] * kQuarterTurnsPerRad, yr);
+            float2 e = phase_pos(tfy * kQuarterTurnsPerRad, yr);
+            if (!(ey_ok && k < kend)) e = make_float2(0.f, 0.f);
             sE[st][ey][ek] = e;
         };
         auto gen_b = [&](int st, int s) {
             const int64_t k = kbeg + (int64_t)s * KC + bk;
-            float2 e0 = make_float2(0.f, 0.f), e1 = e0;
-            if (bx_ok && k < kend) e0 = phase_pos(traj[2 * k] * kQuarterTurnsPerRad, xr);
-            if (bx_ok && k + 1 < kend) e1 = phase_pos(traj[2 * k + 2] * kQuarterTurnsPerRad, xr);
+            float2 e0 = phase_pos(tfx0 * kQuarterTurnsPerRad, xr), e1 = phase_pos(tfx1 * kQuarterTurnsPerRad, xr);
+            if (!(bx_ok && k < kend)) e0 = make_float2(0.f, 0.f);
+            if (!(bx_ok && k + 1 < kend)) e1 = make_float2(0.f, 0.f);
             P::store_b(sB0 + st * P::kBBytes, bx, bk, e0, e1);
         };
+        const float amask = a_ok ? 1.0f : 0.0f;
         auto gen_a = [&](int st, int est) {
             float2 w[KC];
 #pragma unroll
             for (int j = 0; j < KC; j += 2) {
                 const float4 e2 = *reinterpret_cast<const float4*>(&sE[est][ay][j]);
-                w[j] = cmul(dreg[j], make_float2(e2.x, e2.y));
-                w[j + 1] = cmul(dreg[j + 1], make_float2(e2.z, e2.w));
+                w[j] = cscale(cmul(dreg[j], make_float2(e2.x, e2.y)), amask);
+                w[j + 1] = cscale(cmul(dreg[j + 1], make_float2(e2.z, e2.w)), amask);
             }
             P::store_a(sA0 + st * P::kABytes, ac * 32 + ay, w);
         };
@@ -470,16 +492,22 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
             acc_re[t] = floatx16{0};
             acc_im[t] = floatx16{0};
         }
-        // Prologue: E(0), d(0) -> A(0), B(0); E(1), d(1) ready for the loop.
+        // Prologue: E(0), d(0) -> A(0), B(0); E(1), d(1) and the next
+        // trajectory values ready for the loop.
+        load_fy(0);
         gen_e(0, 0);
         load_d(0);
+        load_fx(0);
         __syncthreads();
         gen_a(0, 0);
         gen_b(0, 0);
+        load_fx(1);
         if (nsteps > 1) {
+            load_fy(1);
             gen_e(1, 1);
             load_d(1);
         }
+        load_fy(2);
         __syncthreads();
         for (int s = 0; s < nsteps; ++s) {
             const int cur = s & 1;
@@ -488,8 +516,10 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
             if (s + 1 < nsteps) {
                 gen_a(cur ^ 1, cur ^ 1);              // W(s+1) from d(s+1) and E(s+1)
                 if (s + 2 < nsteps) load_d(s + 2);
-                gen_b(cur ^ 1, s + 1);
-                if (s + 2 < nsteps) gen_e(cur, s + 2);
+                gen_b(cur ^ 1, s + 1);                // uses fx(s+1)
+                if (s + 2 < nsteps) gen_e(cur, s + 2);   // uses fy(s+2)
+                load_fx(s + 2);
+                load_fy(s + 3);
             }
             __syncthreads();
         }
