@@ -178,6 +178,80 @@ int admm_solve(const mri_shape* shape, const mri_c32* smaps, const double* traj,
                mri_c32* x_out, mri_admm_stats* stats_dev,
                void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Request server: continuous batching of independent reconstructions.
+ *
+ * A server owns one device memory pool of `hbm_budget` bytes, allocated once
+ * by mri_server_create (nothing is allocated on the device afterwards), and up
+ * to `max_slots` (<= MRI_SERVER_MAX_SLOTS) concurrently running solves.
+ * Submitted requests wait in a FIFO queue; every mri_server_step() first
+ * admits queued requests in order while a slot is free and the pool can hold
+ * the request's inputs, output and workspace, then runs ONE ADMM iteration
+ * (Alg. 4 with its CG solve) for every active slot: each kernel of the
+ * iteration is one grouped launch over all slots, so their work overlaps on
+ * the device, and the iteration is replayed from a captured HIP graph that is
+ * re-captured only when the set of active slots changes.  Each solve's ADMM
+ * state stays resident in the pool.  After the iteration the step reads the
+ * per-slot stopping flags, copies finished images to host memory and frees
+ * their slots.  A slot's arithmetic does not depend on which other requests
+ * share its launches, so a result is bit-for-bit the same alone and in a mix,
+ * and equal to admm_solve on the same inputs.
+ *
+ * All mri_server_* calls on one server must come from one thread.  Input
+ * arrays of mri_server_submit are HOST pointers and are copied before the
+ * call returns.  Results are copied out to host memory by mri_server_poll.
+ * --------------------------------------------------------------------------- */
+
+#define MRI_SERVER_MAX_SLOTS 16
+
+typedef struct {
+    mri_shape shape;             /* batch must be 1; per-request traj/smaps */
+    const mri_c32* smaps;        /* host [nc][ny][nx] */
+    const double* traj;          /* host [nk][2] */
+    const mri_c32* y;            /* host [nc][nk] */
+    const mri_c32* x0;           /* host [ny][nx] or NULL */
+    mri_admm_params params;      /* params.precision must equal the server's */
+} mri_request;
+
+typedef struct {
+    int32_t queued, active, completed, cancelled;
+    int64_t steps;               /* mri_server_step calls that ran an iteration */
+    int64_t graph_captures;      /* iteration graphs captured */
+    size_t pool_bytes, pool_used;
+} mri_server_info;
+
+enum { MRI_REQ_UNKNOWN = -1, MRI_REQ_QUEUED = 0, MRI_REQ_RUNNING = 1, MRI_REQ_DONE = 2 };
+
+/* Create a server.  precision: MRI_FP32 or MRI_BF16X3 for all its requests.
+ * Errors: MRI_EINVAL (max_slots out of range), MRI_ENOMEM (pool allocation
+ * failed), MRI_EHIP. */
+int mri_server_create(size_t hbm_budget, int max_slots, int precision, void** srv);
+
+/* Queue a request; *id receives its handle.  MRI_ENOMEM if the request alone
+ * can never fit the pool; MRI_EINVAL for bad shape/params (batch != 1). */
+int mri_server_submit(void* srv, const mri_request* req, uint64_t* id);
+
+/* Bytes of pool one request occupies while it runs. */
+size_t mri_server_request_bytes(const mri_shape* shape, int precision);
+
+/* Admit, run one ADMM iteration for all active slots, retire finished ones.
+ * Blocks until the iteration is done.  *n_active (nullable) receives the
+ * number of slots that ran.  Returns 0 with *n_active = 0 when idle. */
+int mri_server_step(void* srv, int* n_active);
+
+/* State of a request (MRI_REQ_*).  When DONE and out_image is non-NULL the
+ * host image [ny][nx] and (if non-NULL) the stats are copied out and the
+ * result is released (a later poll reports MRI_REQ_UNKNOWN). */
+int mri_server_poll(void* srv, uint64_t id, mri_c32* out_image, mri_admm_stats* stats, int* state);
+
+/* Drop a queued or running request (its slot and memory are freed). */
+int mri_server_cancel(void* srv, uint64_t id);
+
+int mri_server_get_info(void* srv, mri_server_info* info);
+
+/* Free the pool and all server resources. */
+int mri_server_destroy(void* srv);
+
 /* Workspace bytes needed by an operation (params may be NULL except for
  * MRI_OP_ADMM).  Returns 0 for an invalid shape. */
 size_t mri_workspace_bytes(const mri_shape* shape, int op, const mri_admm_params* params);

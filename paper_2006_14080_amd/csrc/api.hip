@@ -6,7 +6,7 @@
 #include <cstring>
 #include <string>
 
-#include "solver.h"
+#include "plan.h"
 
 namespace mri {
 namespace {
@@ -23,38 +23,6 @@ int hip_fail(hipError_t e) {
         hipError_t e_ = (call);                    \
         if (e_ != hipSuccess) return hip_fail(e_); \
     } while (0)
-
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-int check_shape(const mri_shape* s) {
-    if (!s) return MRI_EINVAL;
-    if (s->nx < 1 || s->ny < 1 || s->nx > MRI_MAX_DIM || s->ny > MRI_MAX_DIM) return MRI_EINVAL;
-    if (s->ncoils < 1 || s->ncoils > MRI_MAX_COILS) return MRI_EINVAL;
-    if (s->nk < 1 || s->nk > (int64_t)1 << 30) return MRI_EINVAL;
-    if (s->batch < 1 || s->batch > MRI_MAX_BATCH) return MRI_EINVAL;
-    if ((s->traj_batched != 0 && s->traj_batched != 1) || (s->smaps_batched != 0 && s->smaps_batched != 1))
-        return MRI_EINVAL;
-    // grid sizes must fit a 1-D launch
-    if (fwd_tiles(s->nx, s->ny, s->ncoils, s->nk, s->batch) > (int64_t)1 << 30) return MRI_ENOTSUP;
-    return MRI_OK;
-}
-
-int check_precision(int p) {
-    if (p == MRI_FP32) return MRI_OK;
-    if (p == MRI_BF16X3) return MRI_OK;
-    return MRI_EINVAL;
-}
-
-int check_params(const mri_admm_params* p) {
-    if (!p) return MRI_EINVAL;
-    if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return MRI_EINVAL;
-    if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return MRI_EINVAL;
-    if (p->admm_iters < 0 || p->cg_iters < 0) return MRI_EINVAL;
-    if (!(p->rtol >= 0.0) || !(p->atol >= 0.0)) return MRI_EINVAL;
-    if (p->cg_warm_start != 0 && p->cg_warm_start != 1) return MRI_EINVAL;
-    return check_precision(p->precision);
-}
 
 NudftItem base_item(const mri_shape& s, const float2* smaps, const double* traj) {
     NudftItem it;
@@ -81,53 +49,6 @@ NudftTable single_table(const NudftItem& it, int64_t ntiles) {
     t.it[0].tile_begin = 0;
     t.it[0].ntiles = (int32_t)ntiles;
     return t;
-}
-
-size_t forward_ws(const mri_shape& s) {
-    return align_up(sizeof(float2) * (size_t)fwd_wimg_elems(s.nx, s.ny, s.ncoils, s.batch));
-}
-
-size_t adjoint_ws(const mri_shape& s) {
-    int32_t ks, kp;
-    adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, MRI_FP32, &ks, &kp);
-    return align_up(sizeof(float2) * (size_t)s.nx * s.ny * s.batch * adj_partial_planes(s.ncoils, ks));
-}
-
-// ---- ADMM workspace ---------------------------------------------------------
-struct AdmmLayout {
-    size_t rho, rho0, xnew, b, r, p, q, fhd, eta, mu, dtmp, wimg, part, red, sc, total;
-    int32_t ksplit, kper, nblk;
-};
-
-AdmmLayout admm_layout(const mri_shape& s, int precision) {
-    AdmmLayout L;
-    const int64_t npix = (int64_t)s.nx * s.ny;
-    const size_t vec = align_up(sizeof(float2) * npix * s.batch);
-    adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, precision, &L.ksplit, &L.kper);
-    L.nblk = (int32_t)ceil_div(npix, kVecThreads);
-    size_t o = 0;
-    L.rho = o;  o += vec;
-    L.rho0 = o; o += vec;
-    L.xnew = o; o += vec;
-    L.b = o;    o += vec;
-    L.r = o;    o += vec;
-    L.p = o;    o += vec;
-    L.q = o;    o += vec;
-    L.fhd = o;  o += vec;
-    L.eta = o;  o += 2 * vec;
-    L.mu = o;   o += 2 * vec;
-    L.dtmp = o; o += align_up(sizeof(float2) * (size_t)s.ncoils * s.nk * s.batch);
-    L.wimg = o; o += forward_ws(s);
-    L.part = o; o += adjoint_ws(s);
-    L.red = o;  o += align_up(sizeof(double) * 2 * (size_t)L.nblk * s.batch);
-    L.sc = o;   o += align_up(sizeof(SolveScalars) * (size_t)s.batch);
-    L.total = o;
-    return L;
-}
-
-template <class T>
-T* at(void* ws, size_t off) {
-    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
 }
 
 }  // namespace
@@ -172,7 +93,8 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
     it.img = reinterpret_cast<const float2*>(x);
     it.wimg = static_cast<float2*>(ws);
     it.data = reinterpret_cast<float2*>(y);
-    const NudftTable t = single_table(it, fwd_tiles(shape->nx, shape->ny, shape->ncoils, shape->nk, shape->batch));
+    NudftTable t = single_table(it, fwd_tiles(shape->nx, shape->ny, shape->ncoils, shape->nk, shape->batch));
+    t.cw_total = fwd_wimg_elems(shape->nx, shape->ny, shape->ncoils, shape->batch);
     hipStream_t s = static_cast<hipStream_t>(stream);
     MRI_HIP(launch_coil_weight(t, s));
     MRI_HIP(launch_nudft_forward(t, precision, s));
@@ -223,103 +145,24 @@ int admm_solve(const mri_shape* shape, const mri_c32* smaps, const double* traj,
     if (rc) return rc;
     if ((rc = check_params(params))) return rc;
     if (!smaps || !traj || !y || !x_out) return MRI_EINVAL;
-    const mri_shape& sh = *shape;
-    const AdmmLayout L = admm_layout(sh, params->precision);
+    const AdmmLayout L = admm_layout(*shape, params->precision);
     if (!ws || ws_bytes < L.total) return MRI_ENOMEM;
+    SolveBinding bind;
+    bind.shape = *shape;
+    bind.smaps = reinterpret_cast<const float2*>(smaps);
+    bind.traj = traj;
+    bind.y = reinterpret_cast<const float2*>(y);
+    bind.x0 = reinterpret_cast<const float2*>(x0);
+    bind.x_out = reinterpret_cast<float2*>(x_out);
+    bind.stats = stats_dev;
+    bind.params = *params;
+    bind.ws = ws;
+    Plan plan;
+    if ((rc = build_plan(&bind, 1, params->precision, &plan))) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int prec = params->precision;
-    const int64_t npix = (int64_t)sh.nx * sh.ny;
-
-    SolveTable st;
-    std::memset(&st, 0, sizeof(st));
-    st.nitems = 1;
-    st.total_blocks = L.nblk * sh.batch;
-    SolveItem& si = st.it[0];
-    si.nx = sh.nx;
-    si.ny = sh.ny;
-    si.nb = sh.batch;
-    si.nblk = L.nblk;
-    si.block_begin = 0;
-    si.ksplit = adj_partial_planes(sh.ncoils, L.ksplit);
-    si.npix = npix;
-    si.x0 = reinterpret_cast<const float2*>(x0);
-    si.rho = at<float2>(ws, L.rho);
-    si.rho0 = at<float2>(ws, L.rho0);
-    si.xnew = at<float2>(ws, L.xnew);
-    si.b = at<float2>(ws, L.b);
-    si.r = at<float2>(ws, L.r);
-    si.p = at<float2>(ws, L.p);
-    si.q = at<float2>(ws, L.q);
-    si.fhd = at<float2>(ws, L.fhd);
-    si.eta = at<float2>(ws, L.eta);
-    si.mu = at<float2>(ws, L.mu);
-    si.part = at<float2>(ws, L.part);
-    si.red = at<double>(ws, L.red);
-    si.sc = at<SolveScalars>(ws, L.sc);
-    si.x_out = reinterpret_cast<float2*>(x_out);
-    si.stats = stats_dev;
-    si.thr = (float)(params->lambda / params->beta);
-    si.half_beta = (float)(0.5 * params->beta);
-    si.atol2 = params->atol * params->atol;
-    si.rtol2 = params->rtol * params->rtol;
-    si.warm = params->cg_warm_start;
-
-    // NUDFT tables: F^H d (always), the CG start A rho (gated by admm_active),
-    // and the CG step A d (gated by cg_active).
-    const int32_t* admm_flag = &si.sc[0].admm_active;
-    const int32_t* cg_flag = &si.sc[0].cg_active;
-    const int32_t flag_stride = (int32_t)(sizeof(SolveScalars) / sizeof(int32_t));
-    NudftItem base = base_item(sh, reinterpret_cast<const float2*>(smaps), traj);
-    base.ksplit = L.ksplit;
-    base.kper = L.kper;
-    base.part = si.part;
-    base.active_stride = flag_stride;
-    base.wimg = at<float2>(ws, L.wimg);
-    const int64_t ftiles = fwd_tiles(sh.nx, sh.ny, sh.ncoils, sh.nk, sh.batch);
-    const int64_t atiles = adj_tiles_per_split(sh.nx, sh.ny, sh.batch) * L.ksplit;
-
-    NudftItem a_fhd = base;
-    a_fhd.data = const_cast<float2*>(reinterpret_cast<const float2*>(y));
-    a_fhd.active = nullptr;
-    NudftItem f_init = base;
-    f_init.img = params->cg_warm_start ? si.rho : si.rho0;
-    f_init.data = at<float2>(ws, L.dtmp);
-    f_init.active = admm_flag;
-    NudftItem a_init = f_init;
-    NudftItem f_step = base;
-    f_step.img = si.p;
-    f_step.data = at<float2>(ws, L.dtmp);
-    f_step.active = cg_flag;
-    NudftItem a_step = f_step;
-    const NudftTable T_afhd = single_table(a_fhd, atiles);
-    const NudftTable T_finit = single_table(f_init, ftiles);
-    const NudftTable T_ainit = single_table(a_init, atiles);
-    const NudftTable T_fstep = single_table(f_step, ftiles);
-    const NudftTable T_astep = single_table(a_step, atiles);
-
-    MRI_HIP(launch_solve_init(st, s));
-    if (params->admm_iters > 0) {
-        MRI_HIP(launch_nudft_adjoint(T_afhd, prec, s));
-        MRI_HIP(launch_adj_finish(st, kFinishFhd, s));
-    }
-    for (int m = 0; m < params->admm_iters; ++m) {
-        MRI_HIP(launch_mu(st, s));
-        MRI_HIP(launch_rhs(st, s));
-        MRI_HIP(launch_coil_weight(T_finit, s));
-        MRI_HIP(launch_nudft_forward(T_finit, prec, s));
-        MRI_HIP(launch_nudft_adjoint(T_ainit, prec, s));
-        MRI_HIP(launch_adj_finish(st, kFinishCgInit, s));
-        for (int j = 0; j < params->cg_iters; ++j) {
-            MRI_HIP(launch_coil_weight(T_fstep, s));
-            MRI_HIP(launch_nudft_forward(T_fstep, prec, s));
-            MRI_HIP(launch_nudft_adjoint(T_astep, prec, s));
-            MRI_HIP(launch_adj_finish(st, kFinishCgStep, s));
-            MRI_HIP(launch_cg_update(st, s));
-            MRI_HIP(launch_cg_dir(st, s));
-        }
-        MRI_HIP(launch_dual(st, s));
-    }
-    MRI_HIP(launch_solve_final(st, s));
+    MRI_HIP(enqueue_init(plan, s));
+    for (int m = 0; m < params->admm_iters; ++m) MRI_HIP(enqueue_iteration(plan, s));
+    MRI_HIP(enqueue_final(plan, s));
     return MRI_OK;
 }
 

@@ -34,11 +34,13 @@ struct NudftItem {
     int32_t kper;                            // adjoint: samples per split (multiple of 8)
     int32_t tile_begin;                      // first tile of this item
     int32_t ntiles;
+    int64_t cw_begin;                        // first coil-weighting element of this item
 };
 
 struct NudftTable {
     int32_t nitems;
     int32_t total_tiles;
+    int64_t cw_total;                        // coil-weighting elements over all items
     NudftItem it[kMaxItems];
 };
 
@@ -62,7 +64,7 @@ int adj_partial_planes(int nc, int ksplit);
 void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
                int32_t* ksplit, int32_t* kper);
 
-// Pre-pass of the forward for item 0 of t: wimg = smaps (.) img.
+// Pre-pass of the forward for every item of t: wimg = smaps (.) img.
 hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s);
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s);
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s);

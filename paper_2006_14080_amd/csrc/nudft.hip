@@ -224,16 +224,20 @@ struct PolBF16 {
 // Pre-pass of the forward: I[b][g][y][x] = s_g[y][x] x_b[y][x], rows padded to
 // a multiple of KC with zeros so the GEMM loads whole K-steps unguarded.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab, int64_t total) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const NudftItem& it = tab.it[0];
+__global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
+    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gi >= tab.cw_total) return;
+    int k = 0;
+    while (k + 1 < tab.nitems && gi >= tab.it[k + 1].cw_begin) ++k;
+    const NudftItem& it = tab.it[k];
+    const int64_t i = gi - it.cw_begin;
     const int64_t rowlen = ceil_div(it.nx, KC) * KC;
     const int64_t per_coil = rowlen * it.ny;
     const int64_t bg = i / per_coil;
     const int64_t rem = i - bg * per_coil;
     const int y = (int)(rem / rowlen), x = (int)(rem - (int64_t)y * rowlen);
     const int g = (int)(bg % it.nc), b = (int)(bg / it.nc);
+    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
     float2 v = make_float2(0.f, 0.f);
     if (x < it.nx) {
         const int64_t npix = (int64_t)it.nx * it.ny;
@@ -601,10 +605,8 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
 }
 
 hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s) {
-    const NudftItem& it = t.it[0];
-    const int64_t total = fwd_wimg_elems(it.nx, it.ny, it.nc, it.nb);
-    if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, s, t, total);
+    if (t.cw_total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(t.cw_total, 256)), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

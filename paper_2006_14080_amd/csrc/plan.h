@@ -1,0 +1,58 @@
+// Launch plans for ADMM solves: one or more problems (each a batch of slices
+// of one shape) bound to their workspaces, turned into the grouped launch
+// tables of every kernel of Alg. 4.  admm_solve uses a plan of one problem;
+// the request server (server.hip) a plan over its active slots.
+#pragma once
+
+#include "solver.h"
+
+namespace mri {
+
+constexpr size_t kWsAlign = 256;
+inline size_t ws_align(size_t v) { return (v + kWsAlign - 1) / kWsAlign * kWsAlign; }
+
+// Byte offsets of one solve's state inside its workspace.
+struct AdmmLayout {
+    size_t rho, rho0, xnew, b, r, p, q, fhd, eta, mu, dtmp, wimg, part, red, sc, total;
+    int32_t ksplit, kper, nblk, nplanes;
+};
+
+// Argument checks shared by every entry point (MRI_OK or an MRI_E* code).
+int check_shape(const mri_shape* s);
+int check_precision(int p);
+int check_params(const mri_admm_params* p);
+
+AdmmLayout admm_layout(const mri_shape& s, int precision);
+size_t forward_ws(const mri_shape& s);
+size_t adjoint_ws(const mri_shape& s);
+
+// One problem of a plan: inputs and outputs (device pointers) and workspace.
+struct SolveBinding {
+    mri_shape shape;
+    const float2* smaps;
+    const double* traj;
+    const float2* y;
+    const float2* x0;            // may be NULL
+    float2* x_out;
+    mri_admm_stats* stats;       // may be NULL
+    mri_admm_params params;
+    void* ws;                    // admm_layout(shape).total bytes
+};
+
+struct Plan {
+    int precision;
+    int max_cg;                  // CG step launches per ADMM iteration
+    SolveTable st;
+    NudftTable afhd;             // F^H y            (always runs)
+    NudftTable finit, ainit;     // A rho at the CG start (gated by admm_active)
+    NudftTable fstep, astep;     // A d per CG step      (gated by cg_active)
+};
+
+// Build the tables for n <= kMaxItems bindings (all of one precision).
+int build_plan(const SolveBinding* b, int n, int precision, Plan* out);
+
+hipError_t enqueue_init(const Plan& p, hipStream_t s);       // rho, eta, scalars; F^H y
+hipError_t enqueue_iteration(const Plan& p, hipStream_t s);  // one ADMM iteration (eq. (6)-(8))
+hipError_t enqueue_final(const Plan& p, hipStream_t s);      // x_out, stats
+
+}  // namespace mri

@@ -20,6 +20,8 @@ struct SolveScalars {
     int32_t cg_steps;
     int32_t status;      // MRI_OK or MRI_ENUMERIC
     uint32_t counter;    // arrivals of the blocks of the running reduction
+    int32_t cg_it;       // CG steps taken in the current ADMM iteration
+    int32_t pad;
 };
 
 // One solve (nb slices of one shape) as seen by the vector kernels.
@@ -39,6 +41,9 @@ struct SolveItem {
     float half_beta;                // beta / 2
     double atol2, rtol2;
     int32_t warm;
+    int32_t cg_max;                 // CG steps per ADMM iteration (Alg. 2 max_iterations)
+    int32_t admm_max;               // ADMM iterations (Alg. 4 max_iterations)
+    int32_t pad;
 };
 
 struct SolveTable {

@@ -143,6 +143,9 @@ __global__ __launch_bounds__(kVecThreads) void k_solve_init(const SolveTable tab
         s.cg_steps = 0;
         s.status = MRI_OK;
         s.counter = 0u;
+        s.cg_it = 0;
+        s.pad = 0;
+        if (it.admm_max <= 0) s.admm_active = 0;
     }
 }
 
@@ -237,11 +240,13 @@ __global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab
     }
     if (mode == kFinishFhd) return;
     const double atol2 = it.atol2;
+    const int cg_max = it.cg_max;
     if (mode == kFinishCgInit) {
-        reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2](SolveScalars& s, double t0, double) {
+        reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2, cg_max](SolveScalars& s, double t0, double) {
             if (!finite(t0)) { fail_numeric(s); return; }
             s.tau = t0;
-            s.cg_active = t0 > atol2 ? 1 : 0;
+            s.cg_it = 0;
+            s.cg_active = (t0 > atol2 && cg_max > 0) ? 1 : 0;
         });
     } else {
         reduce2_finalize(v0, 0.0, it, l.b, l.blk, [](SolveScalars& s, double t0, double) {
@@ -275,12 +280,14 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(const SolveTable tab)
         v0 = cnorm2(r);
     }
     const double atol2 = it.atol2;
-    reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2](SolveScalars& s, double t0, double) {
+    const int cg_max = it.cg_max;
+    reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2, cg_max](SolveScalars& s, double t0, double) {
         if (!finite(t0)) { fail_numeric(s); return; }
         s.beta_cg = t0 / s.tau;
         s.tau = t0;
         s.cg_steps += 1;
-        s.cg_active = t0 > atol2 ? 1 : 0;
+        s.cg_it += 1;
+        s.cg_active = (t0 > atol2 && s.cg_it < cg_max) ? 1 : 0;
     });
 }
 
@@ -317,12 +324,13 @@ __global__ __launch_bounds__(kVecThreads) void k_dual(const SolveTable tab) {
         it.rho[base + l.pix] = c;
     }
     const double rtol2 = it.rtol2;
-    reduce2_finalize(num, den, it, l.b, l.blk, [rtol2](SolveScalars& s, double t0, double t1) {
+    const int admm_max = it.admm_max;
+    reduce2_finalize(num, den, it, l.b, l.blk, [rtol2, admm_max](SolveScalars& s, double t0, double t1) {
         if (!finite(t0) || !finite(t1)) { fail_numeric(s); return; }
         const double a = t1 > 0.0 ? t0 / t1 : (t0 > 0.0 ? 1.0 : 0.0);
         s.alpha_admm = a;
         s.admm_iters += 1;
-        if (!(a > rtol2)) {
+        if (!(a > rtol2) || s.admm_iters >= admm_max) {
             s.admm_active = 0;
             s.cg_active = 0;
         }
