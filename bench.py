@@ -1,6 +1,7 @@
 """Benchmark: ADMM-TV reconstruction throughput on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3]
+                    [--workload admm256|slices384|serve]
 
 One step = one full admm_solve of the 256x256, 8-coil, 64x512-sample radial
 problem (30 ADMM iterations x 5 CG steps: 1 + 2*30*6 = 361 NUDFT calls),
@@ -13,6 +14,14 @@ steps.  Also reported:
   (BF16 peak for the split-BF16 form, where each product costs three);
 * cpu_baseline -- the FP64 NumPy oracle timed on the host on a bounded sample
   (one ADMM iteration with 5 CG steps of the same problem).
+
+Other workloads (one JSON line each):
+
+* slices384 -- 32 slices of 384x384, 16 coils, 128x768 samples in one batched
+  solve; one step = one ADMM iteration (5 CG) over the whole batch;
+* serve -- a Poisson stream of mixed-shape requests (128/256/384 pixels,
+  4-32 coils, 32-128 spokes x 2N, 30 ADMM x 5 CG) replayed in wall-clock time
+  against the request server; reports p50/p99 latency and recons/s.
 
 Prints one JSON line.
 """
@@ -37,6 +46,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--workload", choices=["admm256", "slices384", "serve"], default="admm256")
+    ap.add_argument("--requests", type=int, default=24, help="serve: requests in the replayed stream")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrival rate (req/s)")
+    ap.add_argument("--slots", type=int, default=8, help="serve: concurrent slots")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: device pool (GiB)")
     ap.add_argument("--kernel-launches", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "nudft_traffic_admm256.json"),
@@ -62,12 +76,107 @@ def cpu_baseline(wl, p):
                       f"{wl.name}, FP64 NumPy, {dt:.1f} s"}
 
 
+def bench_slices(args):
+    """32-slice 384x384 batch: ADMM iterations per second of the whole batch."""
+    import torch
+    from paper_2006_14080_amd import mri, synth
+
+    prec = mri.PRECISIONS[args.precision]
+    wl = synth.SLICES384
+    p = synth.make_problem(wl)
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    sm, tr, truth = g(p.smaps), g(p.traj), g(p.truth)
+    data = mri.nudft_forward(truth, sm, tr, precision=mri.FP32)
+    data += g(p.noise.astype(np.complex64))
+    torch.cuda.synchronize()
+    shape = mri.shape_of((wl.batch, wl.ny, wl.nx), sm, tr)
+    steps, warm = max(1, args.steps), args.warmup
+    # admm_iters = warmup + timed iterations; F^H d and the init run before the timed region
+    stream = torch.cuda.current_stream()
+    out = torch.empty((wl.batch, wl.ny, wl.nx), dtype=torch.complex64, device=dev)
+    timings = {}
+    for n_it in (warm, warm + steps):
+        solver = mri.AdmmSolver(shape, mri.AdmmParams(wl.lam, wl.beta, n_it, wl.cg_iters, precision=prec), device=dev)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        solver.solve(sm, tr, data, out=out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        timings[n_it] = a.elapsed_time(b)
+        st = solver.stats()
+        assert all(s["status"] == 0 and s["admm_iters"] == n_it for s in st), st[:2]
+        del solver
+    ms_step = (timings[warm + steps] - timings[warm]) / steps
+    flop_iter = wl.nudft_flop * 2 * (1 + wl.cg_iters)
+    rec = {
+        "metric": "ADMM iters/s over a 32-slice 384x384 batch (16 coils, 128x768 samples, 5 CG per iteration)",
+        "value": 1e3 / ms_step, "unit": "ADMM iters/s (whole batch)", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == mri.FP32 else "bf16x3",
+        "data": "synthetic (32 seeded ellipse phantoms, shared Gaussian coil maps and golden-angle trajectory)",
+        "config": {"workload": wl.name, "batch": wl.batch, "nx": wl.nx, "ny": wl.ny, "coils": wl.nc,
+                   "spokes": wl.n_spokes, "readout": wl.n_readout, "cg_iters": wl.cg_iters,
+                   "precision": args.precision,
+                   "note": "one step = one full ADMM iteration of all 32 slices; the difference of two solves "
+                           "with warmup and warmup+steps iterations isolates the per-iteration time"},
+        "fp32_equiv_tflops": flop_iter / ms_step / 1e9,
+        "slice_iters_per_s": wl.batch * 1e3 / ms_step,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_serve(args):
+    """Mixed-shape request stream through the continuous-batching server."""
+    import torch
+    from paper_2006_14080_amd import mri, serve, synth
+
+    prec = mri.PRECISIONS[args.precision]
+    reqs = synth.request_stream(args.requests, rate=args.rate)
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    payloads, flop = [], 0.0
+    for r in reqs:   # k-space data: F(phantom) on the GPU plus seeded noise, staged on the host
+        p = synth.make_problem(r.wl)
+        d = mri.nudft_forward(g(p.truth), g(p.smaps), g(p.traj), precision=mri.FP32)[0].cpu().numpy()
+        d = (d + p.noise[0]).astype(np.complex64)
+        payloads.append(dict(smaps=p.smaps, traj=p.traj, data=d,
+                             params=mri.AdmmParams(r.wl.lam, r.wl.beta, r.wl.admm_iters, r.wl.cg_iters)))
+        flop += r.wl.nudft_flop * r.wl.nudft_calls
+    torch.cuda.synchronize()
+    arrivals = [r.arrival for r in reqs]
+    with serve.Server(int(args.budget_gb * (1 << 30)), max_slots=args.slots, precision=prec) as srv:
+        res = serve.replay(srv, arrivals, payloads)
+    rec = {
+        "metric": "served ADMM-TV reconstructions: p50/p99 latency and recons/s",
+        "value": res["recons_per_s"], "unit": "recons/s", "n_gpus": 1, "steps": args.requests, "warmup": 0,
+        "ms_per_step": 1e3 * res["wall_s"] / args.requests, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if prec == mri.FP32 else "bf16x3",
+        "data": "synthetic (seeded phantoms, Gaussian coil maps, golden-angle radial trajectories)",
+        "config": {"workload": f"serve_poisson{args.rate:g}_n{args.requests}", "rate_req_s": args.rate,
+                   "requests": args.requests, "slots": args.slots, "budget_gib": args.budget_gb,
+                   "sizes": [128, 256, 384], "coils": [4, 32], "spokes": [32, 128], "readout": "2N",
+                   "admm_iters": 30, "cg_iters": 5, "precision": args.precision},
+        "latency_p50_s": res["p50_s"], "latency_p99_s": res["p99_s"],
+        "latency_mean_s": float(np.mean(res["latency_s"])), "wall_s": res["wall_s"],
+        "offered_load_tflop_per_s": flop / (max(arrivals) - min(arrivals) + 1e-9) / 1e12,
+        "served_fp32_equiv_tflops": flop / res["wall_s"] / 1e12,
+        "server": {k: int(v) for k, v in res["info"].items()},
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "k-space split is design-only in this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "slices384":
+        return bench_slices(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     import torch
     from paper_2006_14080_amd import mri, synth
 
