@@ -241,11 +241,16 @@ def main():
     else:
         achieved_pipe = achieved
     peak = PEAK_TFLOPS[args.precision]
+    # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (copy-calibrated), valid
+    # only while the kernel sources match the ones the counters were taken on.
     traffic = None
     if os.path.exists(args.traffic):
         try:
+            from paper_2006_14080_amd.profsum import kernel_fingerprint
             with open(args.traffic) as f:
-                traffic = json.load(f).get(args.precision, {}).get(dom_name)
+                rec_t = json.load(f).get(args.precision, {})
+            if rec_t.get("kernel_sources_sha256") == kernel_fingerprint():
+                traffic = rec_t.get(dom_name, {}).get("bytes")
         except Exception:
             traffic = None
 

@@ -88,6 +88,7 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
     if (rc) return rc;
     if ((rc = check_precision(precision))) return rc;
     if (!x || !smaps || !traj || !y) return MRI_EINVAL;
+    if (fwd_wimg_elems(shape->nx, shape->ny, shape->ncoils, shape->batch) >= ((int64_t)1 << 31)) return MRI_ENOTSUP;
     if (!ws || ws_bytes < forward_ws(*shape)) return MRI_ENOMEM;
     NudftItem it = base_item(*shape, reinterpret_cast<const float2*>(smaps), traj);
     it.img = reinterpret_cast<const float2*>(x);

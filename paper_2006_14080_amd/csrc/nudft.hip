@@ -59,6 +59,7 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
 // LDS planes with K contiguous: A (Ar, Ai); B (Br, Bi, -Bi).  Lanes 0-31 read
 // plane Ar / Br / Bi, lanes 32-63 read Ai / -Bi / Br, four K values per read.
 struct PolF32 {
+    static constexpr bool kPrioritiseMfma = false;   // measured: no gain (MFMA-bound already)
     static constexpr int kABytes = 2 * kRows * RS * 4;
     static constexpr int kBBytes = 3 * 64 * RS * 4;
 
@@ -117,6 +118,7 @@ struct PolF32 {
 // so 8 complex K values cost 3 MFMAs per accumulator with no idle slot.
 // LDS keeps every 16-byte operand chunk ready: A [h][m][row], B [var][h][m][col].
 struct PolBF16 {
+    static constexpr bool kPrioritiseMfma = true;    // measured: +5% on the VALU-heavy forward
     static constexpr int kABytes = 2 * 3 * kRows * 16;
     static constexpr int kBBytes = 2 * 2 * 3 * 64 * 16;
 
@@ -224,27 +226,36 @@ struct PolBF16 {
 // Pre-pass of the forward: I[b][g][y][x] = s_g[y][x] x_b[y][x], rows padded to
 // a multiple of KC with zeros so the GEMM loads whole K-steps unguarded.
 // ---------------------------------------------------------------------------
+// Each thread forms four consecutive pixels of one padded row (the pitch is a
+// multiple of 8, so a group never crosses a row) and stores them as two
+// 16-byte writes.
 __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
-    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (gi >= tab.cw_total) return;
+    const int64_t gq = (int64_t)blockIdx.x * 256 + threadIdx.x;   // index of a 4-pixel group
+    if (gq * 4 >= tab.cw_total) return;
+    const int64_t gi = gq * 4;
     int k = 0;
     while (k + 1 < tab.nitems && gi >= tab.it[k + 1].cw_begin) ++k;
     const NudftItem& it = tab.it[k];
-    const int64_t i = gi - it.cw_begin;
-    const int64_t rowlen = ceil_div(it.nx, KC) * KC;
-    const int64_t per_coil = rowlen * it.ny;
-    const int64_t bg = i / per_coil;
-    const int64_t rem = i - bg * per_coil;
-    const int y = (int)(rem / rowlen), x = (int)(rem - (int64_t)y * rowlen);
-    const int g = (int)(bg % it.nc), b = (int)(bg / it.nc);
+    const int i = (int)(gi - it.cw_begin);           // < 2^31 per item (checked on the host)
+    const int rowlen = (int)ceil_div(it.nx, KC) * KC;
+    const int per_coil = rowlen * it.ny;
+    const int bg = i / per_coil;
+    const int rem = i - bg * per_coil;
+    const int y = rem / rowlen, x0 = rem - y * rowlen;
+    const int g = bg % it.nc, b = bg / it.nc;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
-    float2 v = make_float2(0.f, 0.f);
-    if (x < it.nx) {
-        const int64_t npix = (int64_t)it.nx * it.ny;
-        const int64_t p = (int64_t)y * it.nx + x;
-        v = cmul(it.smaps[b * it.smaps_bs + g * npix + p], it.img[b * npix + p]);
+    const int64_t npix = (int64_t)it.nx * it.ny;
+    const float2* sm = it.smaps + b * it.smaps_bs + g * npix + (int64_t)y * it.nx;
+    const float2* im = it.img + b * npix + (int64_t)y * it.nx;
+    float2 v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int x = x0 + j;
+        v[j] = x < it.nx ? cmul(sm[x], im[x]) : make_float2(0.f, 0.f);
     }
-    it.wimg[i] = v;
+    float4* dst = reinterpret_cast<float4*>(it.wimg + i);
+    dst[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+    dst[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
 }
 
 // ---------------------------------------------------------------------------
@@ -339,8 +350,10 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             const int cur = s & 1;
             const bool more = s + 1 < nsteps;
             if (more) load_a(s + 1);
+            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);   // MFMA burst ahead of the co-resident wave's VALU
             P::mma(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (kNT * 32), wn * 32, lane, nvalid,
                    acc_re, acc_im);
+            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
             if (more) {
                 store_a(cur ^ 1);
                 store_b(cur ^ 1, s + 1);
@@ -515,8 +528,10 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
         __syncthreads();
         for (int s = 0; s < nsteps; ++s) {
             const int cur = s & 1;
+            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);   // MFMA burst ahead of the co-resident wave's VALU
             P::mma(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (kNT * 32), wn * 32, lane, nvalid,
                    acc_re, acc_im);
+            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
             if (s + 1 < nsteps) {
                 gen_a(cur ^ 1, cur ^ 1);              // W(s+1) from d(s+1) and E(s+1)
                 if (s + 2 < nsteps) load_d(s + 2);
@@ -606,7 +621,7 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
 
 hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s) {
     if (t.cw_total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(t.cw_total, 256)), dim3(256), 0, s, t);
+    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(t.cw_total, 4 * 256)), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

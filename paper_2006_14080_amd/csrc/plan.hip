@@ -95,10 +95,13 @@ void append(NudftTable& t, const NudftItem& it, int64_t ntiles, int64_t cw_elems
 
 int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
     if (n < 1 || n > kMaxItems) return MRI_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if ((int64_t)bind[i].shape.nx * bind[i].shape.ny >= ((int64_t)1 << 31)) return MRI_ENOTSUP;
     Plan& P = *out;
     std::memset(&P, 0, sizeof(P));
     P.precision = precision;
     int64_t blocks = 0, tiles_f = 0, tiles_a = 0;
+    int32_t slices = 0;
     for (int i = 0; i < n; ++i) {
         const SolveBinding& B = bind[i];
         const mri_shape& sh = B.shape;
@@ -138,6 +141,8 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         si.warm = prm.cg_warm_start;
         si.cg_max = prm.cg_iters;
         si.admm_max = prm.admm_iters;
+        si.slice_begin = slices;
+        slices += sh.batch;
         blocks += (int64_t)L.nblk * sh.batch;
         P.max_cg = std::max(P.max_cg, (int)prm.cg_iters);
 
@@ -160,6 +165,7 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         const int64_t ft = fwd_tiles(sh.nx, sh.ny, sh.ncoils, sh.nk, sh.batch);
         const int64_t at_ = adj_tiles_per_split(sh.nx, sh.ny, sh.batch) * L.ksplit;
         const int64_t cw = fwd_wimg_elems(sh.nx, sh.ny, sh.ncoils, sh.batch);
+        if (cw >= ((int64_t)1 << 31)) return MRI_ENOTSUP;     // 32-bit indexing inside an item
         tiles_f += ft;
         tiles_a += at_;
 
@@ -184,6 +190,7 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         return MRI_ENOTSUP;
     P.st.nitems = n;
     P.st.total_blocks = (int32_t)blocks;
+    P.st.total_slices = slices;
     return MRI_OK;
 }
 
@@ -207,15 +214,19 @@ hipError_t enqueue_iteration(const Plan& p, hipStream_t s) {
     PLAN_TRY(launch_nudft_forward(p.finit, p.precision, s));
     PLAN_TRY(launch_nudft_adjoint(p.ainit, p.precision, s));
     PLAN_TRY(launch_adj_finish(p.st, kFinishCgInit, s));
+    PLAN_TRY(launch_finalize(p.st, kFinCgInit, s));
     for (int j = 0; j < p.max_cg; ++j) {
         PLAN_TRY(launch_coil_weight(p.fstep, s));
         PLAN_TRY(launch_nudft_forward(p.fstep, p.precision, s));
         PLAN_TRY(launch_nudft_adjoint(p.astep, p.precision, s));
         PLAN_TRY(launch_adj_finish(p.st, kFinishCgStep, s));
+        PLAN_TRY(launch_finalize(p.st, kFinCgStep, s));
         PLAN_TRY(launch_cg_update(p.st, s));
+        PLAN_TRY(launch_finalize(p.st, kFinCgUpdate, s));
         PLAN_TRY(launch_cg_dir(p.st, s));
     }
     PLAN_TRY(launch_dual(p.st, s));
+    PLAN_TRY(launch_finalize(p.st, kFinDual, s));
     return hipSuccess;
 }
 

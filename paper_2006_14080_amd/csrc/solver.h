@@ -19,7 +19,7 @@ struct SolveScalars {
     int32_t admm_iters;
     int32_t cg_steps;
     int32_t status;      // MRI_OK or MRI_ENUMERIC
-    uint32_t counter;    // arrivals of the blocks of the running reduction
+    uint32_t counter;    // unused (kept for layout)
     int32_t cg_it;       // CG steps taken in the current ADMM iteration
     int32_t pad;
 };
@@ -43,18 +43,20 @@ struct SolveItem {
     int32_t warm;
     int32_t cg_max;                 // CG steps per ADMM iteration (Alg. 2 max_iterations)
     int32_t admm_max;               // ADMM iterations (Alg. 4 max_iterations)
-    int32_t pad;
+    int32_t slice_begin;            // first slice of this item in a grouped launch
 };
 
 struct SolveTable {
     int32_t nitems;
     int32_t total_blocks;
+    int32_t total_slices;
     SolveItem it[kMaxItems];
 };
 
 constexpr int kVecThreads = 256;   // one pixel per thread
 
 enum FinishMode { kFinishFhd = 0, kFinishCgInit = 1, kFinishCgStep = 2 };
+enum FinalizeMode { kFinCgInit = 0, kFinCgStep = 1, kFinCgUpdate = 2, kFinDual = 3 };
 
 hipError_t launch_solve_init(const SolveTable& t, hipStream_t s);
 hipError_t launch_mu(const SolveTable& t, hipStream_t s);
@@ -63,6 +65,7 @@ hipError_t launch_adj_finish(const SolveTable& t, int mode, hipStream_t s);
 hipError_t launch_cg_update(const SolveTable& t, hipStream_t s);
 hipError_t launch_cg_dir(const SolveTable& t, hipStream_t s);
 hipError_t launch_dual(const SolveTable& t, hipStream_t s);
+hipError_t launch_finalize(const SolveTable& t, int mode, hipStream_t s);
 hipError_t launch_solve_final(const SolveTable& t, hipStream_t s);
 
 hipError_t launch_sum_partials(const float2* part, int ksplit, int64_t n, float2* out, hipStream_t s);

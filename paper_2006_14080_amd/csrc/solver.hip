@@ -5,9 +5,11 @@
 //
 // All are memory-bound, one pixel per thread, coalesced along x.  Vector
 // arithmetic is FP32; inner products and norms accumulate in FP64 and are
-// summed in a fixed order: wave shuffles, waves in index order, then the
-// per-block partials in block order by the last block to arrive (an integer
-// arrival counter; no floating-point atomics), so results are reproducible.
+// summed in a fixed order: wave shuffles, waves in index order, per-block
+// partials written to memory, then one finalize block per slice (k_finalize)
+// sums the partials in block order and applies the scalar logic of Alg. 2 /
+// Alg. 4.  No atomics and no device-wide fences, so results are reproducible
+// and nothing serialises the grid.
 #include "device.h"
 #include "solver.h"
 
@@ -16,7 +18,7 @@ namespace {
 
 struct Loc {
     int item, b, blk;
-    int64_t pix;
+    int pix;            // pixel within the slice (npix < 2^31)
     bool valid;
 };
 
@@ -30,8 +32,8 @@ __device__ __forceinline__ Loc locate(const SolveTable& t) {
     l.item = i;
     l.b = local / it.nblk;
     l.blk = local % it.nblk;
-    l.pix = (int64_t)l.blk * kVecThreads + threadIdx.x;
-    l.valid = l.pix < it.npix;
+    l.pix = l.blk * kVecThreads + (int)threadIdx.x;
+    l.valid = l.pix < (int)it.npix;
     return l;
 }
 
@@ -39,8 +41,8 @@ __device__ __forceinline__ Loc locate(const SolveTable& t) {
 struct Nb {
     int64_t xp, xm, yp, ym;   // (i, j+1), (i, j-1), (i+1, j), (i-1, j)
 };
-__device__ __forceinline__ Nb neighbours(int64_t p, int nx, int ny) {
-    const int i = (int)(p / nx), j = (int)(p - (int64_t)i * nx);
+__device__ __forceinline__ Nb neighbours(int p, int nx, int ny) {
+    const int i = p / nx, j = p - i * nx;
     const int jp = j + 1 == nx ? 0 : j + 1, jm = j == 0 ? nx - 1 : j - 1;
     const int ip = i + 1 == ny ? 0 : i + 1, im = i == 0 ? ny - 1 : i - 1;
     Nb n;
@@ -55,13 +57,10 @@ __device__ __forceinline__ double cnorm2(float2 a) {
     return (double)a.x * a.x + (double)a.y * a.y;
 }
 
-// Block partials (two FP64 values) -> per-slice partial array; the last block
-// of the slice to arrive sums all partials in block order and calls fin().
-template <class Fin>
-__device__ __forceinline__ void reduce2_finalize(double v0, double v1, const SolveItem& it, int b, int blk, Fin fin) {
+// Block partials (two FP64 values per block) -> red[b][0..1][blk], summed in
+// a fixed order: wave shuffles, then the block's waves in index order.
+__device__ __forceinline__ void block_partials(double v0, double v1, const SolveItem& it, int b, int blk) {
     __shared__ double sm[2][kVecThreads / 64];
-    __shared__ double tot[2][kVecThreads / 64];
-    __shared__ int is_last;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     v0 = wave_sum(v0);
     v1 = wave_sum(v1);
@@ -70,7 +69,6 @@ __device__ __forceinline__ void reduce2_finalize(double v0, double v1, const Sol
         sm[1][w] = v1;
     }
     __syncthreads();
-    double* red = it.red + (int64_t)b * 2 * it.nblk;
     if (tid == 0) {
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -78,37 +76,9 @@ __device__ __forceinline__ void reduce2_finalize(double v0, double v1, const Sol
             s0 += sm[0][k];
             s1 += sm[1][k];
         }
+        double* red = it.red + (int64_t)b * 2 * it.nblk;
         red[blk] = s0;
         red[it.nblk + blk] = s1;
-        __threadfence();
-        const uint32_t old = __hip_atomic_fetch_add(&it.sc[b].counter, 1u, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (old == (uint32_t)(it.nblk - 1));
-    }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-    double a0 = 0.0, a1 = 0.0;
-    for (int k = tid; k < it.nblk; k += kVecThreads) {
-        a0 += __builtin_nontemporal_load(&red[k]);
-        a1 += __builtin_nontemporal_load(&red[it.nblk + k]);
-    }
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
-    if (lane == 0) {
-        tot[0][w] = a0;
-        tot[1][w] = a1;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double t0 = 0.0, t1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < kVecThreads / 64; ++k) {
-            t0 += tot[0][k];
-            t1 += tot[1][k];
-        }
-        fin(it.sc[b], t0, t1);
-        it.sc[b].counter = 0u;
     }
 }
 
@@ -238,27 +208,7 @@ __global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab
             }
         }
     }
-    if (mode == kFinishFhd) return;
-    const double atol2 = it.atol2;
-    const int cg_max = it.cg_max;
-    if (mode == kFinishCgInit) {
-        reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2, cg_max](SolveScalars& s, double t0, double) {
-            if (!finite(t0)) { fail_numeric(s); return; }
-            s.tau = t0;
-            s.cg_it = 0;
-            s.cg_active = (t0 > atol2 && cg_max > 0) ? 1 : 0;
-        });
-    } else {
-        reduce2_finalize(v0, 0.0, it, l.b, l.blk, [](SolveScalars& s, double t0, double) {
-            if (!finite(t0)) { fail_numeric(s); return; }
-            s.pap = t0;
-            if (t0 > 0.0) {
-                s.alpha_cg = s.tau / t0;
-            } else {
-                s.cg_active = 0;    // breakdown: d^H A d <= 0
-            }
-        });
-    }
+    if (mode != kFinishFhd) block_partials(v0, 0.0, it, l.b, l.blk);
 }
 
 // ---- Alg. 2 step: x += alpha d; r -= alpha A d; tau' = r^H r ------------------
@@ -279,16 +229,7 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(const SolveTable tab)
         it.r[o] = r;
         v0 = cnorm2(r);
     }
-    const double atol2 = it.atol2;
-    const int cg_max = it.cg_max;
-    reduce2_finalize(v0, 0.0, it, l.b, l.blk, [atol2, cg_max](SolveScalars& s, double t0, double) {
-        if (!finite(t0)) { fail_numeric(s); return; }
-        s.beta_cg = t0 / s.tau;
-        s.tau = t0;
-        s.cg_steps += 1;
-        s.cg_it += 1;
-        s.cg_active = (t0 > atol2 && s.cg_it < cg_max) ? 1 : 0;
-    });
+    block_partials(v0, 0.0, it, l.b, l.blk);
 }
 
 // ---- Alg. 2 direction: d = r + (tau'/tau) d -----------------------------------
@@ -323,18 +264,79 @@ __global__ __launch_bounds__(kVecThreads) void k_dual(const SolveTable tab) {
         den = cnorm2(old);
         it.rho[base + l.pix] = c;
     }
-    const double rtol2 = it.rtol2;
-    const int admm_max = it.admm_max;
-    reduce2_finalize(num, den, it, l.b, l.blk, [rtol2, admm_max](SolveScalars& s, double t0, double t1) {
-        if (!finite(t0) || !finite(t1)) { fail_numeric(s); return; }
-        const double a = t1 > 0.0 ? t0 / t1 : (t0 > 0.0 ? 1.0 : 0.0);
-        s.alpha_admm = a;
-        s.admm_iters += 1;
-        if (!(a > rtol2) || s.admm_iters >= admm_max) {
-            s.admm_active = 0;
-            s.cg_active = 0;
+    block_partials(num, den, it, l.b, l.blk);
+}
+
+// ---- per-slice scalar logic of Alg. 2 / Alg. 4 ----------------------------------
+// One block per slice sums the block partials of the preceding kernel in
+// block order and updates the slice's scalars.  It runs under the same
+// condition as the kernel that wrote the partials (flags are unchanged in
+// between), so every written partial is consumed exactly once.
+__global__ __launch_bounds__(kVecThreads) void k_finalize(const SolveTable tab, int mode) {
+    const int g = blockIdx.x;
+    int i = 0;
+    while (i + 1 < tab.nitems && g >= tab.it[i + 1].slice_begin) ++i;
+    const SolveItem& it = tab.it[i];
+    const int b = g - it.slice_begin;
+    SolveScalars& s = it.sc[b];
+    const bool run = (mode == kFinCgInit || mode == kFinDual) ? s.admm_active != 0 : s.cg_active != 0;
+    if (!run) return;
+    __shared__ double tot[2][kVecThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double* red = it.red + (int64_t)b * 2 * it.nblk;
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = tid; k < it.nblk; k += kVecThreads) {
+        a0 += red[k];
+        a1 += red[it.nblk + k];
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    if (lane == 0) {
+        tot[0][w] = a0;
+        tot[1][w] = a1;
+    }
+    __syncthreads();
+    if (tid != 0) return;
+    double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kVecThreads / 64; ++k) {
+        t0 += tot[0][k];
+        t1 += tot[1][k];
+    }
+    if (!finite(t0) || !finite(t1)) {
+        fail_numeric(s);
+        return;
+    }
+    switch (mode) {
+        case kFinCgInit:            // tau = r^H r of r = b - A x0
+            s.tau = t0;
+            s.cg_it = 0;
+            s.cg_active = (t0 > it.atol2 && it.cg_max > 0) ? 1 : 0;
+            break;
+        case kFinCgStep:            // alpha = tau / Re(d^H A d), breakdown guard
+            s.pap = t0;
+            if (t0 > 0.0)
+                s.alpha_cg = s.tau / t0;
+            else
+                s.cg_active = 0;
+            break;
+        case kFinCgUpdate:          // tau' = r^H r; beta = tau'/tau; stopping tests
+            s.beta_cg = t0 / s.tau;
+            s.tau = t0;
+            s.cg_steps += 1;
+            s.cg_it += 1;
+            s.cg_active = (t0 > it.atol2 && s.cg_it < it.cg_max) ? 1 : 0;
+            break;
+        default: {                  // kFinDual: alpha = ||rho' - rho||^2 / ||rho||^2 (Alg. 4)
+            const double a = t1 > 0.0 ? t0 / t1 : (t0 > 0.0 ? 1.0 : 0.0);
+            s.alpha_admm = a;
+            s.admm_iters += 1;
+            if (!(a > it.rtol2) || s.admm_iters >= it.admm_max) {
+                s.admm_active = 0;
+                s.cg_active = 0;
+            }
         }
-    });
+    }
 }
 
 // ---- output and per-slice report ---------------------------------------------
@@ -372,29 +374,29 @@ __global__ __launch_bounds__(kVecThreads) void k_sum_partials(const float2* __re
     out[i] = make_float2((float)sr, (float)si);
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_tv_forward(int nx, int ny, int64_t n, const float2* __restrict__ x,
+__global__ __launch_bounds__(kVecThreads) void k_tv_forward(int nx, int ny, const float2* __restrict__ x,
                                                             float2* __restrict__ g) {
-    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
-    if (i >= n) return;
-    const int64_t npix = (int64_t)nx * ny;
-    const int64_t b = i / npix, p = i - b * npix;
+    const int npix = nx * ny;
+    const int p = blockIdx.x * kVecThreads + threadIdx.x;
+    if (p >= npix) return;
+    const int64_t b = blockIdx.y;
     const float2* xb = x + b * npix;
     const Nb nb = neighbours(p, nx, ny);
     const float2 c = xb[p];
     g[2 * b * npix + p] = csub(xb[nb.xp], c);
-    g[2 * b * npix + npix + p] = csub(xb[nb.yp], c);
+    g[(2 * b + 1) * npix + p] = csub(xb[nb.yp], c);
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_tv_adjoint(int nx, int ny, int64_t n, const float2* __restrict__ g,
+__global__ __launch_bounds__(kVecThreads) void k_tv_adjoint(int nx, int ny, const float2* __restrict__ g,
                                                             float2* __restrict__ x) {
-    const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
-    if (i >= n) return;
-    const int64_t npix = (int64_t)nx * ny;
-    const int64_t b = i / npix, p = i - b * npix;
+    const int npix = nx * ny;
+    const int p = blockIdx.x * kVecThreads + threadIdx.x;
+    if (p >= npix) return;
+    const int64_t b = blockIdx.y;
     const float2* g0 = g + 2 * b * npix;
     const float2* g1 = g0 + npix;
     const Nb nb = neighbours(p, nx, ny);
-    x[i] = cadd(csub(g0[nb.xm], g0[p]), csub(g1[nb.ym], g1[p]));
+    x[b * npix + p] = cadd(csub(g0[nb.xm], g0[p]), csub(g1[nb.ym], g1[p]));
 }
 
 inline dim3 grid_of(const SolveTable& t) { return dim3(t.total_blocks); }
@@ -429,6 +431,10 @@ hipError_t launch_dual(const SolveTable& t, hipStream_t s) {
     hipLaunchKernelGGL(k_dual, grid_of(t), dim3(kVecThreads), 0, s, t);
     return hipGetLastError();
 }
+hipError_t launch_finalize(const SolveTable& t, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(t.total_slices), dim3(kVecThreads), 0, s, t, mode);
+    return hipGetLastError();
+}
 hipError_t launch_solve_final(const SolveTable& t, hipStream_t s) {
     hipLaunchKernelGGL(k_solve_final, grid_of(t), dim3(kVecThreads), 0, s, t);
     return hipGetLastError();
@@ -440,17 +446,17 @@ hipError_t launch_sum_partials(const float2* part, int ksplit, int64_t n, float2
     return hipGetLastError();
 }
 hipError_t launch_tv_forward(int nx, int ny, int nb, const float2* x, float2* g, hipStream_t s) {
-    const int64_t n = (int64_t)nx * ny * nb;
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tv_forward, dim3((unsigned)ceil_div(n, kVecThreads)), dim3(kVecThreads), 0, s,
-                       nx, ny, n, x, g);
+    const int64_t npix = (int64_t)nx * ny;
+    if (npix <= 0 || nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_forward, dim3((unsigned)ceil_div(npix, kVecThreads), nb), dim3(kVecThreads), 0, s,
+                       nx, ny, x, g);
     return hipGetLastError();
 }
 hipError_t launch_tv_adjoint(int nx, int ny, int nb, const float2* g, float2* x, hipStream_t s) {
-    const int64_t n = (int64_t)nx * ny * nb;
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_tv_adjoint, dim3((unsigned)ceil_div(n, kVecThreads)), dim3(kVecThreads), 0, s,
-                       nx, ny, n, g, x);
+    const int64_t npix = (int64_t)nx * ny;
+    if (npix <= 0 || nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tv_adjoint, dim3((unsigned)ceil_div(npix, kVecThreads), nb), dim3(kVecThreads), 0, s,
+                       nx, ny, g, x);
     return hipGetLastError();
 }
 

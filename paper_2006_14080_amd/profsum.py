@@ -3,6 +3,12 @@
     python -m paper_2006_14080_amd.profsum stats <run_kernel_stats.csv> --cmd "<command>" [--top N]
     python -m paper_2006_14080_amd.profsum pmc <run_counter_collection.csv> --cmd "<command>"
     python -m paper_2006_14080_amd.profsum traffic <fetch.csv> <write.csv> --cmd "<command>" [--json out.json --key fp32]
+    python -m paper_2006_14080_amd.profsum vecbw <run_kernel_stats.csv> --cmd "<command>" --npix N --coils C --planes P
+
+``vecbw`` turns the durations of the solver's memory-bound kernels into
+achieved bandwidth from their algorithmic bytes per pixel (listed in
+VEC_BYTES; N = pixels of all slices, C = coils, P = adjoint partial images
+per slice), against the 8 TB/s HBM peak.
 
 ``stats`` lists per-kernel call counts and durations; ``pmc`` averages every
 counter per kernel over its dispatches (FETCH_SIZE / WRITE_SIZE are KiB per
@@ -47,6 +53,34 @@ def pmc(path):
     return out
 
 
+# Algorithmic bytes per pixel (complex64 = 8 B) of each memory-bound kernel:
+# every array element the kernel must read or write once.
+VEC_BYTES = {
+    "k_mu": lambda c, p: 8 + 16 + 16,                  # rho, eta -> mu
+    "k_rhs": lambda c, p: 8 + 16 + 16 + 8,             # F^H d, mu, eta -> b
+    "k_adj_finish": lambda c, p: 8 * p + 8 + 8,        # partial images, d -> A d (step mode)
+    "k_cg_update": lambda c, p: 4 * 8 + 2 * 8,         # x, r, d, A d -> x, r
+    "k_cg_dir": lambda c, p: 2 * 8 + 8,                # r, d -> d
+    "k_dual": lambda c, p: 8 + 16 + 16 + 8 + 16 + 8,   # x, mu, eta, rho -> eta, rho
+    "k_coil_weight": lambda c, p: 8 + 16 * c,          # x, s -> s (.) x
+}
+HBM_PEAK = 8.0e12
+
+
+def vecbw(path, npix, coils, planes):
+    rows = list(csv.DictReader(open(path)))
+    out = [f"{'kernel':16s} {'calls':>6s} {'avg_us':>9s} {'bytes/px':>9s} {'GB/s':>8s} {'of 8 TB/s':>9s}"]
+    for r in rows:
+        k = short(r["Name"]).split("(")[0]
+        if k not in VEC_BYTES:
+            continue
+        b = VEC_BYTES[k](coils, planes)
+        us = float(r["AverageNs"]) / 1e3
+        gbs = b * npix / (us * 1e-6) / 1e9
+        out.append(f"{k:16s} {int(r['Calls']):6d} {us:9.2f} {b:9d} {gbs:8.1f} {gbs * 1e9 / HBM_PEAK:9.1%}")
+    return out
+
+
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_BYTES = 256 * 1024 * 1024      # the driver's calibration copy reads and writes 256 MiB
 
@@ -62,6 +96,21 @@ def _per_kernel(path, counter):
         val[k] += float(r["Counter_Value"])
         disp[k].add(r["Dispatch_Id"])
     return {k: v / len(disp[k]) for k, v in val.items()}   # KiB per dispatch
+
+
+KERNEL_SOURCES = ["nudft.hip", "phase.h", "device.h", "internal.h"]
+
+
+def kernel_fingerprint() -> str:
+    """sha256 over the sources of the NUDFT kernels (traffic is void once they change)."""
+    import hashlib
+    import os
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for n in KERNEL_SOURCES:
+        with open(os.path.join(base, n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def traffic(fetch_csv, write_csv):
@@ -84,17 +133,28 @@ def traffic(fetch_csv, write_csv):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "pmc", "traffic"])
+    ap.add_argument("mode", choices=["stats", "pmc", "traffic", "vecbw"])
     ap.add_argument("csv")
     ap.add_argument("csv2", nargs="?")
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--top", type=int, default=14)
     ap.add_argument("--json")
     ap.add_argument("--key")
+    ap.add_argument("--npix", type=int)
+    ap.add_argument("--coils", type=int)
+    ap.add_argument("--planes", type=int)
     a = ap.parse_args()
+    if a.mode == "vecbw":
+        print("# solver memory-bound kernels: achieved bandwidth from algorithmic bytes")
+        print(f"# command: {a.cmd}")
+        print(f"# pixels (all slices) = {a.npix}, coils = {a.coils}, adjoint partial images per slice = {a.planes}")
+        for line in vecbw(a.csv, a.npix, a.coils, a.planes):
+            print(line)
+        return 0
     if a.mode == "traffic":
         t = traffic(a.csv, a.csv2)
         t["command"] = a.cmd
+        t["kernel_sources_sha256"] = kernel_fingerprint()
         if a.json:
             import json
             import os
