@@ -58,7 +58,10 @@ int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb);
 // Elements of the coil-weighted image the forward reads (rows padded to a K-step).
 int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb);
 int64_t adj_tiles_per_split(int nx, int ny, int nb);
-// Partial images the adjoint writes per slice: one per (sample split, group of 8 coils).
+// Row tiles per wave of the forward (by ny) and of the adjoint (by coil count).
+int fwd_nt(int ny);
+int adj_nt(int nc);
+// Partial images the adjoint writes per slice: one per (sample split, coil group).
 int adj_partial_planes(int nc, int ksplit);
 // Choose the sample-range split of the adjoint for one problem.
 void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,

@@ -52,7 +52,8 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
 // (Br, -Bi) and (Bi, Br) that produce the real and imaginary accumulators.
 //   store_a(stage, row, v[KC])        one row of A, K values 0..KC-1
 //   store_b(stage, col, kp, e0, e1)   B column col, K values kp, kp+1
-//   mma(a, b, arow0, bcol0, lane, nvalid, acc_re, acc_im)
+//   mma<NT>(a, b, arow0, bcol0, lane, ntile, acc_re, acc_im)  NT row tiles
+//   from row arow0 (skipped as a whole when the wave has no live tile).
 // ---------------------------------------------------------------------------
 
 // FP32: v_mfma_f32_32x32x2_f32, K-slot 0 = real part, slot 1 = imaginary.
@@ -78,26 +79,27 @@ struct PolF32 {
         *reinterpret_cast<float2*>(p + 64 * RS) = make_float2(e0.y, e1.y);
         *reinterpret_cast<float2*>(p + 128 * RS) = make_float2(-e0.y, -e1.y);
     }
+    template <int NT>
     __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
-                                               int nvalid, floatx16 (&acc_re)[kNT], floatx16 (&acc_im)[kNT]) {
+                                               int ntile, floatx16 (&acc_re)[NT], floatx16 (&acc_im)[NT]) {
         const int h = lane >> 5, l32 = lane & 31;
         const float* ap = reinterpret_cast<const float*>(a) + (h * kRows + arow0 + l32) * RS;
         const float* bre = reinterpret_cast<const float*>(b) + ((h ? 2 : 0) * 64 + bcol0 + l32) * RS;
         const float* bim = reinterpret_cast<const float*>(b) + ((h ? 0 : 1) * 64 + bcol0 + l32) * RS;
-        // Row tiles past the valid range hold zeros, so a wave with any live
-        // tile runs all of them (branch-free); a wave with none skips the stage.
-        if (__builtin_amdgcn_readfirstlane(nvalid) == 0) return;
+        // A wave with no live row tile skips the stage; otherwise all NT tiles
+        // run (rows past the valid range hold zeros) as one branch-free burst.
+        if (__builtin_amdgcn_readfirstlane(ntile) == 0) return;
 #pragma unroll
         for (int kq = 0; kq < KC; kq += 4) {
             const floatx4 br = *reinterpret_cast<const floatx4*>(bre + kq);
             const floatx4 bi = *reinterpret_cast<const floatx4*>(bim + kq);
-            floatx4 av[kNT];
+            floatx4 av[NT];
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) av[t] = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
+            for (int t = 0; t < NT; ++t) av[t] = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
 #pragma unroll
-                for (int t = 0; t < kNT; ++t) {
+                for (int t = 0; t < NT; ++t) {
                     acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t][j], br[j], acc_re[t], 0, 0, 0);
                     acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t][j], bi[j], acc_im[t], 0, 0, 0);
                 }
@@ -199,22 +201,23 @@ struct PolBF16 {
             }
         }
     }
+    template <int NT>
     __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
-                                               int nvalid, floatx16 (&acc_re)[kNT], floatx16 (&acc_im)[kNT]) {
+                                               int ntile, floatx16 (&acc_re)[NT], floatx16 (&acc_im)[NT]) {
         const int h = lane >> 5, l32 = lane & 31;
         const char* bre = b + ((h * 3) * 64 + bcol0 + l32) * 16;
         const char* bim = b + (((2 + h) * 3) * 64 + bcol0 + l32) * 16;
         const char* ap = a + ((h * 3) * kRows + arow0 + l32) * 16;
-        if (__builtin_amdgcn_readfirstlane(nvalid) == 0) return;   // see PolF32::mma
+        if (__builtin_amdgcn_readfirstlane(ntile) == 0) return;   // see PolF32::mma
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const bf16x8 br = *reinterpret_cast<const bf16x8*>(bre + m * 64 * 16);
             const bf16x8 bi = *reinterpret_cast<const bf16x8*>(bim + m * 64 * 16);
-            bf16x8 av[kNT];
+            bf16x8 av[NT];
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) av[t] = *reinterpret_cast<const bf16x8*>(ap + (m * kRows + t * 32) * 16);
+            for (int t = 0; t < NT; ++t) av[t] = *reinterpret_cast<const bf16x8*>(ap + (m * kRows + t * 32) * 16);
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) {
+            for (int t = 0; t < NT; ++t) {
                 acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[t], br, acc_re[t], 0, 0, 0);
                 acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[t], bi, acc_im[t], 0, 0, 0);
             }
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
 // ---------------------------------------------------------------------------
 // Forward: tile = (slice, coil, 64 samples); rows = every y in passes of 256.
 // ---------------------------------------------------------------------------
-template <class P>
+template <class P, int NT>
 __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
     __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + P::kBBytes)];
     __shared__ float2 red[2][kFwdCols];
@@ -303,11 +306,15 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
     const int nsteps = pitch / KC;
     float2 dsum = make_float2(0.f, 0.f);
 
-    for (int y0 = 0; y0 < ny; y0 += kRows) {
-        const int wrow0 = y0 + wm * (kNT * 32);
-        const int nvalid = wrow0 >= ny ? 0 : min(kNT, (ny - wrow0 + 31) / 32);
+    // Rows are covered in passes of 2 * NT * 32; the host picks NT per shape so
+    // the passes are even (e.g. 384 rows = 2 passes of 192, NT = 3).
+    constexpr int nt = NT;
+    constexpr int prows = 2 * NT * 32;
+    for (int y0 = 0; y0 < ny; y0 += prows) {
+        const int wrow0 = y0 + wm * (nt * 32);
+        const int nvalid = wrow0 >= ny ? 0 : min(nt, (ny - wrow0 + 31) / 32);
         const int yrow = y0 + tid;
-        const bool row_ok = yrow < ny;
+        const bool row_ok = yrow < ny && tid < prows;
         // rows past ny load row ny-1 (always in bounds) and are zeroed when staged
         const float4* src = reinterpret_cast<const float4*>(wi + (int64_t)min(yrow, ny - 1) * pitch);
         const float rmask = row_ok ? 1.0f : 0.0f;
@@ -336,9 +343,9 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             P::store_b(sB0 + st * P::kBBytes, pc, pj, e0, e1);
         };
 
-        floatx16 acc_re[kNT], acc_im[kNT];
+        floatx16 acc_re[NT], acc_im[NT];
 #pragma unroll
-        for (int t = 0; t < kNT; ++t) {
+        for (int t = 0; t < NT; ++t) {
             acc_re[t] = floatx16{0};
             acc_im[t] = floatx16{0};
         }
@@ -351,7 +358,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             const bool more = s + 1 < nsteps;
             if (more) load_a(s + 1);
             if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);   // MFMA burst ahead of the co-resident wave's VALU
-            P::mma(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (kNT * 32), wn * 32, lane, nvalid,
+            P::template mma<NT>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32), wn * 32, lane, nvalid,
                    acc_re, acc_im);
             if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
             if (more) {
@@ -368,7 +375,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         if (e_ok && nvalid > 0) {
             const int ybase = wrow0 + h * 4 - yh;
             const float2 e0 = phase_neg(fy4, (double)ybase);
-            float2 f1[4], f8[4], f32[kNT];
+            float2 f1[4], f8[4], f32[NT];
             f1[0] = f8[0] = f32[0] = make_float2(1.f, 0.f);
 #pragma unroll
             for (int j = 1; j < 4; ++j) {
@@ -376,9 +383,9 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
                 f8[j] = phase_neg(fy4, (double)(8 * j));
             }
 #pragma unroll
-            for (int j = 1; j < kNT; ++j) f32[j] = phase_neg(fy4, (double)(32 * j));
+            for (int j = 1; j < NT; ++j) f32[j] = phase_neg(fy4, (double)(32 * j));
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) {
+            for (int t = 0; t < NT; ++t) {
                 if (t < nvalid) {
                     const float2 et = cmul(e0, f32[t]);
 #pragma unroll
@@ -408,7 +415,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
 // Adjoint: tile = (slice, split, 32 y rows, 64 x columns); GEMM rows are
 // (coil, y) for a group of 8 coils per pass.
 // ---------------------------------------------------------------------------
-template <class P>
+template <class P, int NT>
 __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + P::kBBytes)];
     __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC + 2];   // conj(Ey) for the next A (padded rows)
@@ -452,10 +459,15 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     const bool bx_ok = x0 + bx < nx;
     const int xe = x0 + wn * 32 + l32;                   // epilogue column
 
-    const int ncgroups = (nc + kAdjCoilGroup - 1) / kAdjCoilGroup;
-    for (int g0 = 0; g0 < nc; g0 += kAdjCoilGroup) {
-        const int ncg = min(kAdjCoilGroup, nc - g0);
-        const int nvalid = max(0, min(kNT, ncg - wm * kNT));
+    // Coils run in groups of 2 * NT, split between the two row-waves (NT coils
+    // each); the host picks NT per coil count so the groups are even
+    // (e.g. 12 coils = 2 groups of 6, NT = 3).
+    constexpr int nt = NT;
+    constexpr int gsz = 2 * NT;
+    const int ncgroups = (nc + gsz - 1) / gsz;
+    for (int gi = 0, g0 = 0; g0 < nc; ++gi, g0 += gsz) {
+        const int ncg = min(gsz, nc - g0);
+        const int nvalid = max(0, min(nt, ncg - wm * nt));
         const bool a_ok = ac < ncg;
         const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk;
         float2 dreg[KC];
@@ -503,9 +515,9 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
             P::store_a(sA0 + st * P::kABytes, ac * 32 + ay, w);
         };
 
-        floatx16 acc_re[kNT], acc_im[kNT];
+        floatx16 acc_re[NT], acc_im[NT];
 #pragma unroll
-        for (int t = 0; t < kNT; ++t) {
+        for (int t = 0; t < NT; ++t) {
             acc_re[t] = floatx16{0};
             acc_im[t] = floatx16{0};
         }
@@ -529,7 +541,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
         for (int s = 0; s < nsteps; ++s) {
             const int cur = s & 1;
             if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);   // MFMA burst ahead of the co-resident wave's VALU
-            P::mma(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (kNT * 32), wn * 32, lane, nvalid,
+            P::template mma<NT>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32), wn * 32, lane, nvalid,
                    acc_re, acc_im);
             if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
             if (s + 1 < nsteps) {
@@ -550,9 +562,9 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
         for (int i = 0; i < 16; ++i) part[i] = make_float2(0.f, 0.f);
         if (xe < nx) {
 #pragma unroll
-            for (int t = 0; t < kNT; ++t) {
+            for (int t = 0; t < NT; ++t) {
                 if (t < nvalid) {
-                    const int g = g0 + wm * kNT + t;
+                    const int g = g0 + wm * nt + t;
                     const float2* sg = sm + (int64_t)g * npix;
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
@@ -571,7 +583,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
         }
         __syncthreads();
         if (wm == 0 && xe < nx) {
-            const int plane = sp * ncgroups + g0 / kAdjCoilGroup;
+            const int plane = sp * ncgroups + gi;
             float2* out = it.part + ((int64_t)plane * it.nb + b) * npix;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
@@ -593,8 +605,21 @@ int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb) {
     return (int64_t)nb * nc * ny * (ceil_div(nx, KC) * KC);
 }
 
+int fwd_nt(int ny) {
+    const int npass = (int)ceil_div(ny, kRows);
+    const int nt = (int)ceil_div(ny, 64 * npass);
+    return nt < 2 ? 2 : nt;
+}
+
+int adj_nt(int nc) {
+    const int ngroups = (int)ceil_div(nc, kAdjCoilGroup);
+    const int gsz = (int)ceil_div(nc, ngroups);
+    const int nt = (gsz + 1) / 2;
+    return nt < 2 ? 2 : nt;
+}
+
 int adj_partial_planes(int nc, int ksplit) {
-    return ksplit * (int)ceil_div(nc, kAdjCoilGroup);
+    return ksplit * (int)ceil_div(nc, 2 * adj_nt(nc));
 }
 
 int64_t adj_tiles_per_split(int nx, int ny, int nb) {
@@ -625,22 +650,67 @@ hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s) {
     return hipGetLastError();
 }
 
+namespace {
+
+// Launch one kernel variant per row-tile class: items are grouped by their NT
+// (each class keeps its own contiguous tile numbering).
+template <class Pick, class Launch>
+hipError_t launch_by_nt(const NudftTable& t, Pick nt_of, Launch launch) {
+    for (int nt = 2; nt <= kNT; ++nt) {
+        NudftTable sub;
+        sub.nitems = 0;
+        sub.total_tiles = 0;
+        sub.cw_total = 0;
+        for (int i = 0; i < t.nitems; ++i) {
+            if (nt_of(t.it[i]) != nt) continue;
+            sub.it[sub.nitems] = t.it[i];
+            sub.it[sub.nitems].tile_begin = sub.total_tiles;
+            sub.total_tiles += t.it[i].ntiles;
+            ++sub.nitems;
+        }
+        if (sub.total_tiles == 0) continue;
+        const hipError_t e = launch(sub, nt);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <class P>
+hipError_t fwd_variant(const NudftTable& t, int nt, hipStream_t s) {
+    const dim3 g(t.total_tiles), b(kThreads);
+    if (nt == 2) hipLaunchKernelGGL((nudft_fwd<P, 2>), g, b, 0, s, t);
+    else if (nt == 3) hipLaunchKernelGGL((nudft_fwd<P, 3>), g, b, 0, s, t);
+    else hipLaunchKernelGGL((nudft_fwd<P, 4>), g, b, 0, s, t);
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t adj_variant(const NudftTable& t, int nt, hipStream_t s) {
+    const dim3 g(t.total_tiles), b(kThreads);
+    if (nt == 2) hipLaunchKernelGGL((nudft_adj<P, 2>), g, b, 0, s, t);
+    else if (nt == 3) hipLaunchKernelGGL((nudft_adj<P, 3>), g, b, 0, s, t);
+    else hipLaunchKernelGGL((nudft_adj<P, 4>), g, b, 0, s, t);
+    return hipGetLastError();
+}
+
+}  // namespace
+
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s) {
     if (t.total_tiles <= 0) return hipSuccess;
-    if (precision == MRI_BF16X3)
-        hipLaunchKernelGGL(nudft_fwd<PolBF16>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
-    else
-        hipLaunchKernelGGL(nudft_fwd<PolF32>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
-    return hipGetLastError();
+    return launch_by_nt(t, [](const NudftItem& it) { return fwd_nt(it.ny); },
+                        [&](const NudftTable& sub, int nt) {
+                            return precision == MRI_BF16X3 ? fwd_variant<PolBF16>(sub, nt, s)
+                                                           : fwd_variant<PolF32>(sub, nt, s);
+                        });
 }
 
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s) {
     if (t.total_tiles <= 0) return hipSuccess;
-    if (precision == MRI_BF16X3)
-        hipLaunchKernelGGL(nudft_adj<PolBF16>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
-    else
-        hipLaunchKernelGGL(nudft_adj<PolF32>, dim3(t.total_tiles), dim3(kThreads), 0, s, t);
-    return hipGetLastError();
+    return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); },
+                        [&](const NudftTable& sub, int nt) {
+                            return precision == MRI_BF16X3 ? adj_variant<PolBF16>(sub, nt, s)
+                                                           : adj_variant<PolF32>(sub, nt, s);
+                        });
 }
 
 }  // namespace mri
