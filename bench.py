@@ -1,6 +1,6 @@
 """Benchmark: ADMM-TV reconstruction throughput on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3|fp16x3]
                     [--workload admm256|slices384|serve]
 
 One step = one full admm_solve of the 256x256, 8-coil, 64x512-sample radial
@@ -11,7 +11,7 @@ steps.  Also reported:
 * roofline -- the dominant NUDFT kernel: algorithmic flop per launch
   (8 * nk * nx * ny * nc) over its average launch time, measured with HIP
   events on the stream it runs on, against the MI355X dense FP32 MFMA peak
-  (BF16 peak for the split-BF16 form, where each product costs three);
+  (BF16 / FP16 peak for the split forms, where each product costs three);
 * cpu_baseline -- the FP64 NumPy oracle timed on the host on a bounded sample
   (one ADMM iteration with 5 CG steps of the same problem).
 
@@ -36,7 +36,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6}   # MI355X dense MFMA peaks
+PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6}   # MI355X dense MFMA peaks
+DTYPE = {"fp32": "f32", "bf16x3": "bf16x3", "fp16x3": "f16x3"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -45,7 +46,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp16x3"], default="fp32")
     ap.add_argument("--workload", choices=["admm256", "slices384", "serve"], default="admm256")
     ap.add_argument("--requests", type=int, default=24, help="serve: requests in the replayed stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrival rate (req/s)")
@@ -114,7 +115,7 @@ def bench_slices(args):
         "metric": "ADMM iters/s over a 32-slice 384x384 batch (16 coils, 128x768 samples, 5 CG per iteration)",
         "value": 1e3 / ms_step, "unit": "ADMM iters/s (whole batch)", "n_gpus": 1, "steps": steps,
         "warmup": warm, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if prec == mri.FP32 else "bf16x3",
+        "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic (32 seeded ellipse phantoms, shared Gaussian coil maps and golden-angle trajectory)",
         "config": {"workload": wl.name, "batch": wl.batch, "nx": wl.nx, "ny": wl.ny, "coils": wl.nc,
                    "spokes": wl.n_spokes, "readout": wl.n_readout, "cg_iters": wl.cg_iters,
@@ -152,7 +153,7 @@ def bench_serve(args):
         "metric": "served ADMM-TV reconstructions: p50/p99 latency and recons/s",
         "value": res["recons_per_s"], "unit": "recons/s", "n_gpus": 1, "steps": args.requests, "warmup": 0,
         "ms_per_step": 1e3 * res["wall_s"] / args.requests, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if prec == mri.FP32 else "bf16x3",
+        "vs_baseline": None, "dtype": DTYPE[args.precision],
         "data": "synthetic (seeded phantoms, Gaussian coil maps, golden-angle radial trajectories)",
         "config": {"workload": f"serve_poisson{args.rate:g}_n{args.requests}", "rate_req_s": args.rate,
                    "requests": args.requests, "slots": args.slots, "budget_gib": args.budget_gb,
@@ -236,8 +237,8 @@ def main():
     flop = wl.nudft_flop
     dom_name, dom_ms = ("nudft_forward", fwd_ms) if fwd_ms >= adj_ms else ("nudft_adjoint", adj_ms)
     achieved = flop / (dom_ms / 1e3) / 1e12
-    if prec == mri.BF16X3:
-        achieved_pipe = achieved * 3.0      # three BF16 products per real product
+    if prec in (mri.BF16X3, mri.FP16X3):
+        achieved_pipe = achieved * 3.0      # three 16-bit products per real product
     else:
         achieved_pipe = achieved
     peak = PEAK_TFLOPS[args.precision]
@@ -265,7 +266,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == mri.FP32 else "bf16x3",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic (seeded ellipse phantom, Gaussian coil maps, golden-angle radial trajectory, "
                 "complex Gaussian noise 1e-3)",
         "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "coils": wl.nc, "spokes": wl.n_spokes,

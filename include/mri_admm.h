@@ -60,8 +60,12 @@ typedef struct {
 /* Arithmetic of the NUDFT matrix products. */
 enum {
     MRI_FP32 = 0,   /* FP32 MFMA products, FP32 accumulation */
-    MRI_BF16X3 = 1  /* split-BF16 compensated products (hi*hi + hi*lo + lo*hi)
-                       on BF16 MFMA, FP32 accumulation (Sec. II-A) */
+    MRI_BF16X3 = 1, /* split-BF16 compensated products (hi*hi + hi*lo + lo*hi)
+                       on BF16 MFMA, FP32 accumulation (Sec. II-A); about 16
+                       bits per operand */
+    MRI_FP16X3 = 2  /* the same split products with fp16 parts on FP16 MFMA
+                       (same rate): about 22 bits per operand; operands are
+                       scaled by exact powers of two into fp16's range */
 };
 
 enum {
@@ -89,10 +93,13 @@ enum { MRI_OP_FORWARD = 0, MRI_OP_ADJOINT = 1, MRI_OP_ADMM = 2 };
  * separable form of Alg. 1, T = E_x (s (.) x)^T followed by a row sum
  * against E_y.
  *   x [B][ny][nx], smaps, traj as above, y [B][nc][nk] (written).
- *   precision: MRI_FP32 or MRI_BF16X3.
+ *   precision: MRI_FP32, MRI_BF16X3 or MRI_FP16X3.
  *   ws/ws_bytes: workspace of at least mri_workspace_bytes(shape,
  *   MRI_OP_FORWARD, NULL) bytes; it receives the coil-weighted images
- *   s (.) x (rows padded to a multiple of 8 pixels).
+ *   s (.) x (rows padded to a multiple of 8 pixels): 8 B per coil pixel
+ *   in FP32, 12 B in the split forms, which store them already split into
+ *   16-bit high/low parts in the matrix cores' operand order (MRI_FP16X3
+ *   adds one float scale per row).
  * Errors: MRI_EINVAL, MRI_ENOTSUP, MRI_ENOMEM, MRI_EHIP.
  */
 int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps,
@@ -222,7 +229,8 @@ typedef struct {
 
 enum { MRI_REQ_UNKNOWN = -1, MRI_REQ_QUEUED = 0, MRI_REQ_RUNNING = 1, MRI_REQ_DONE = 2 };
 
-/* Create a server.  precision: MRI_FP32 or MRI_BF16X3 for all its requests.
+/* Create a server.  precision: MRI_FP32, MRI_BF16X3 or MRI_FP16X3 for all
+ * its requests.
  * Errors: MRI_EINVAL (max_slots out of range), MRI_ENOMEM (pool allocation
  * failed), MRI_EHIP. */
 int mri_server_create(size_t hbm_budget, int max_slots, int precision, void** srv);

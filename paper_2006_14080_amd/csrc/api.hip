@@ -88,7 +88,9 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
     if (rc) return rc;
     if ((rc = check_precision(precision))) return rc;
     if (!x || !smaps || !traj || !y) return MRI_EINVAL;
-    if (fwd_wimg_elems(shape->nx, shape->ny, shape->ncoils, shape->batch) >= ((int64_t)1 << 31)) return MRI_ENOTSUP;
+    if (fwd_wimg_elems(shape->nx, shape->ny, shape->ncoils, shape->batch) >= ((int64_t)1 << 31) ||
+        fwd_split_units(shape->nx, shape->ny, shape->ncoils, shape->batch) >= ((int64_t)1 << 31))
+        return MRI_ENOTSUP;
     if (!ws || ws_bytes < forward_ws(*shape)) return MRI_ENOMEM;
     NudftItem it = base_item(*shape, reinterpret_cast<const float2*>(smaps), traj);
     it.img = reinterpret_cast<const float2*>(x);
@@ -97,7 +99,7 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
     NudftTable t = single_table(it, fwd_tiles(shape->nx, shape->ny, shape->ncoils, shape->nk, shape->batch));
     t.cw_total = fwd_wimg_elems(shape->nx, shape->ny, shape->ncoils, shape->batch);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    MRI_HIP(launch_coil_weight(t, s));
+    MRI_HIP(launch_coil_weight(t, precision, s));
     MRI_HIP(launch_nudft_forward(t, precision, s));
     return MRI_OK;
 }

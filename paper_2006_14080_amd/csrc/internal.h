@@ -59,7 +59,28 @@ int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb);
 int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb);
 int64_t adj_tiles_per_split(int nx, int ny, int nb);
 // Row tiles per wave of the forward (by ny) and of the adjoint (by coil count).
-int fwd_nt(int ny);
+__host__ __device__ inline int fwd_nt(int ny) {
+    const int npass = (ny + 255) / 256;
+    const int nt = (ny + 64 * npass - 1) / (64 * npass);
+    return nt < 2 ? 2 : nt;
+}
+// Rows of the forward's pre-split operand: whole passes of 2 * fwd_nt * 32.
+__host__ __device__ inline int fwd_padded_rows(int ny) {
+    const int prows = 2 * fwd_nt(ny) * 32;
+    return (ny + prows - 1) / prows * prows;
+}
+// (slice, coil, K-step, row) units of the split (16-bit) pre-pass; 96 bytes each.
+__host__ __device__ inline int64_t fwd_split_units(int nx, int ny, int nc, int nb) {
+    return (int64_t)nb * nc * ((nx + kKStep - 1) / kKStep) * fwd_padded_rows(ny);
+}
+// Split-FP16 form: inverse row scales, float [nb][nc][padded rows], stored
+// right after the 96-byte units (16-byte aligned).
+__host__ __device__ inline int64_t fwd_rowscale_floats(int ny, int nc, int nb) {
+    return (int64_t)nb * nc * fwd_padded_rows(ny);
+}
+__host__ __device__ inline float* fwd_rowscale(float2* wimg, int nx, int ny, int nc, int nb) {
+    return reinterpret_cast<float*>(reinterpret_cast<char*>(wimg) + 96 * fwd_split_units(nx, ny, nc, nb));
+}
 int adj_nt(int nc);
 // Partial images the adjoint writes per slice: one per (sample split, coil group).
 int adj_partial_planes(int nc, int ksplit);
@@ -67,8 +88,9 @@ int adj_partial_planes(int nc, int ksplit);
 void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
                int32_t* ksplit, int32_t* kper);
 
-// Pre-pass of the forward for every item of t: wimg = smaps (.) img.
-hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s);
+// Pre-pass of the forward for every item of t: wimg = smaps (.) img (FP32
+// rows, or split operand chunks for MRI_BF16X3 / MRI_FP16X3).
+hipError_t launch_coil_weight(const NudftTable& t, int precision, hipStream_t s);
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s);
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s);
 

@@ -61,6 +61,9 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
 // plane Ar / Br / Bi, lanes 32-63 read Ai / -Bi / Br, four K values per read.
 struct PolF32 {
     static constexpr bool kPrioritiseMfma = false;   // measured: no gain (MFMA-bound already)
+    static constexpr bool kPresplitA = false;        // forward A staged from the FP32 coil-weighted image
+    static constexpr bool kScaled = false;
+    static constexpr float kBScale = 1.0f;
     static constexpr int kABytes = 2 * kRows * RS * 4;
     static constexpr int kBBytes = 3 * 64 * RS * 4;
 
@@ -108,43 +111,64 @@ struct PolF32 {
     }
 };
 
-// Split-BF16 (Sec. II-A "decomposition and accumulation"): each FP32 value
-// a = hi + lo with hi = bf16(a), lo = bf16(a - hi) (round to nearest even);
-// a real product a b is formed as hi_a hi_b + hi_a lo_b + lo_a hi_b, FP32
-// accumulation.  v_mfma_f32_32x32x16_bf16 takes 8 K-slots per lane half; the
-// six products of a complex K value for one accumulator occupy six slots:
+// Split products (Sec. II-A "decomposition and accumulation"): each FP32
+// value a = hi + lo with hi = T(a), lo = T(a - hi) (round to nearest even) for
+// a 16-bit type T; a real product a b is formed as hi_a hi_b + hi_a lo_b +
+// lo_a hi_b with FP32 accumulation.  v_mfma_f32_32x32x16_{bf16,f16} take 8
+// K-slots per lane half; the six products of a complex K value for one
+// accumulator occupy six slots:
 //   A    : [ArH, ArH, ArL, AiH, AiH, AiL]
 //   B_re : [BrH, BrL, BrH, -BiH, -BiL, -BiH]   -> Ar Br - Ai Bi
 //   B_im : [BiH, BiL, BiH, BrH, BrL, BrH]      -> Ar Bi + Ai Br
 // Lane half h takes complex K values 4h..4h+3 (24 slots = 3 instructions),
 // so 8 complex K values cost 3 MFMAs per accumulator with no idle slot.
 // LDS keeps every 16-byte operand chunk ready: A [h][m][row], B [var][h][m][col].
-struct PolBF16 {
+//
+// T = bf16 (the paper's form): 8 significant bits per part, so hi + lo holds
+// about 16 bits of each operand; it needs no scaling (bf16 has the FP32
+// exponent range).
+// T = fp16 (same MFMA rate on gfx950): 11 bits per part, about 22 bits per
+// operand, but a narrow exponent range, so operands are scaled by powers of
+// two (exact) into [2^14, 2^15) before the split and the results scaled back:
+// phases by 2^14; the forward's coil-weighted image per row (pre-pass); the
+// adjoint's data per coil over each workgroup's sample range.  Parts that
+// fall below fp16's normal range then carry less than 2^-28 of an operand's
+// magnitude.
+template <class T, bool Scaled>
+struct PolSplit {
+    typedef T vec8 __attribute__((ext_vector_type(8)));
+    typedef T vec4 __attribute__((ext_vector_type(4)));
     static constexpr bool kPrioritiseMfma = true;    // measured: +5% on the VALU-heavy forward
+    static constexpr bool kPresplitA = true;         // forward A pre-split into operand chunks once per call
+    static constexpr bool kScaled = Scaled;
+    static constexpr float kBScale = Scaled ? 16384.0f : 1.0f;   // phases (|e| <= 1) -> [-2^14, 2^14]
     static constexpr int kABytes = 2 * 3 * kRows * 16;
     static constexpr int kBBytes = 2 * 2 * 3 * 64 * 16;
 
     struct Sp {
-        __bf16 h, l;
+        T h, l;
     };
     __device__ __forceinline__ static Sp split(float a) {
         Sp s;
-        s.h = static_cast<__bf16>(a);
-        s.l = static_cast<__bf16>(a - static_cast<float>(s.h));
+        s.h = static_cast<T>(a);
+        s.l = static_cast<T>(a - static_cast<float>(s.h));
         return s;
     }
     // slot value of term t (0..5) for the A operand
-    __device__ __forceinline__ static __bf16 a_term(int t, Sp r, Sp i) {
+    __device__ __forceinline__ static T a_term(int t, Sp r, Sp i) {
         return t == 0 || t == 1 ? r.h : t == 2 ? r.l : t == 5 ? i.l : i.h;
     }
-    __device__ __forceinline__ static __bf16 bre_term(int t, Sp r, Sp i) {
+    __device__ __forceinline__ static T bre_term(int t, Sp r, Sp i) {
         return t == 0 || t == 2 ? r.h : t == 1 ? r.l : t == 4 ? -i.l : -i.h;
     }
-    __device__ __forceinline__ static __bf16 bim_term(int t, Sp r, Sp i) {
+    __device__ __forceinline__ static T bim_term(int t, Sp r, Sp i) {
         return t == 0 || t == 2 ? i.h : t == 1 ? i.l : t == 4 ? r.l : r.h;
     }
+    __device__ __forceinline__ static floatx16 mfma(vec8 a, vec8 b, floatx16 c);
 
-    __device__ __forceinline__ static void store_a(char* st, int row, const float2 (&v)[KC]) {
+    // One row of A (K values 0..KC-1) as six 16-byte chunks; chunk (h, m) of
+    // row r sits at ((h*3+m)*rows + r)*16.
+    __device__ __forceinline__ static void store_a_rows(char* st, int row, int rows, const float2 (&v)[KC]) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             Sp r[4], i[4];
@@ -155,49 +179,52 @@ struct PolBF16 {
             }
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                bf16x8 c;
+                vec8 c;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int slot = 8 * m + j, q = slot / 6, t = slot % 6;
                     c[j] = a_term(t, r[q], i[q]);
                 }
-                *reinterpret_cast<bf16x8*>(st + ((h * 3 + m) * kRows + row) * 16) = c;
+                *reinterpret_cast<vec8*>(st + ((int64_t)(h * 3 + m) * rows + row) * 16) = c;
             }
         }
     }
+    __device__ __forceinline__ static void store_a(char* st, int row, const float2 (&v)[KC]) {
+        store_a_rows(st, row, kRows, v);
+    }
     __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
         const int h = kp >> 2;
-        const Sp r0 = split(e0.x), i0 = split(e0.y), r1 = split(e1.x), i1 = split(e1.y);
+        const Sp r0 = split(e0.x * kBScale), i0 = split(e0.y * kBScale);
+        const Sp r1 = split(e1.x * kBScale), i1 = split(e1.y * kBScale);
 #pragma unroll
         for (int var = 0; var < 2; ++var) {
-            __bf16 sl[12];
+            T sl[12];
 #pragma unroll
             for (int t = 0; t < 6; ++t) {
                 sl[t] = var == 0 ? bre_term(t, r0, i0) : bim_term(t, r0, i0);
                 sl[6 + t] = var == 0 ? bre_term(t, r1, i1) : bim_term(t, r1, i1);
             }
             char* base = st + (((var * 2 + h) * 3) * 64 + col) * 16;
-            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
             if ((kp & 3) == 0) {
                 // slots 0..11: chunk 0 whole, first half of chunk 1
-                bf16x8 c0;
-                bf16x4 c1;
+                vec8 c0;
+                vec4 c1;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) c0[j] = sl[j];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) c1[j] = sl[8 + j];
-                *reinterpret_cast<bf16x8*>(base) = c0;
-                *reinterpret_cast<bf16x4*>(base + 64 * 16) = c1;
+                *reinterpret_cast<vec8*>(base) = c0;
+                *reinterpret_cast<vec4*>(base + 64 * 16) = c1;
             } else {
                 // slots 12..23: second half of chunk 1, chunk 2 whole
-                bf16x4 c1;
-                bf16x8 c2;
+                vec4 c1;
+                vec8 c2;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) c1[j] = sl[j];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) c2[j] = sl[4 + j];
-                *reinterpret_cast<bf16x4*>(base + 64 * 16 + 8) = c1;
-                *reinterpret_cast<bf16x8*>(base + 2 * 64 * 16) = c2;
+                *reinterpret_cast<vec4*>(base + 64 * 16 + 8) = c1;
+                *reinterpret_cast<vec8*>(base + 2 * 64 * 16) = c2;
             }
         }
     }
@@ -211,19 +238,40 @@ struct PolBF16 {
         if (__builtin_amdgcn_readfirstlane(ntile) == 0) return;   // see PolF32::mma
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const bf16x8 br = *reinterpret_cast<const bf16x8*>(bre + m * 64 * 16);
-            const bf16x8 bi = *reinterpret_cast<const bf16x8*>(bim + m * 64 * 16);
-            bf16x8 av[NT];
+            const vec8 br = *reinterpret_cast<const vec8*>(bre + m * 64 * 16);
+            const vec8 bi = *reinterpret_cast<const vec8*>(bim + m * 64 * 16);
+            vec8 av[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) av[t] = *reinterpret_cast<const bf16x8*>(ap + (m * kRows + t * 32) * 16);
+            for (int t = 0; t < NT; ++t) av[t] = *reinterpret_cast<const vec8*>(ap + (m * kRows + t * 32) * 16);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[t], br, acc_re[t], 0, 0, 0);
-                acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[t], bi, acc_im[t], 0, 0, 0);
+                acc_re[t] = mfma(av[t], br, acc_re[t]);
+                acc_im[t] = mfma(av[t], bi, acc_im[t]);
             }
         }
     }
 };
+
+template <>
+__device__ __forceinline__ floatx16 PolSplit<__bf16, false>::mfma(vec8 a, vec8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ floatx16 PolSplit<_Float16, true>::mfma(vec8 a, vec8 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+typedef PolSplit<__bf16, false> PolBF16;
+typedef PolSplit<_Float16, true> PolF16;
+
+// Power-of-two scale exponent that maps magnitudes <= m into [2^14, 2^15)
+// (kept within FP32's normal range; m = 0 or non-finite gives a finite scale).
+__device__ __forceinline__ int split_scale_exp(float m) {
+    int e = 0;
+    frexpf(m, &e);                       // m = f 2^e, f in [0.5, 1)
+    const int s = 15 - e;
+    return s > 126 ? 126 : s < -126 ? -126 : s;
+}
 
 // ---------------------------------------------------------------------------
 // Pre-pass of the forward: I[b][g][y][x] = s_g[y][x] x_b[y][x], rows padded to
@@ -259,6 +307,103 @@ __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
     float4* dst = reinterpret_cast<float4*>(it.wimg + i);
     dst[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
     dst[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
+}
+
+// Split-BF16 form of the pre-pass: s_g (.) x_b is split and packed once per
+// call into the forward's A-operand chunks, in LDS order, so every sample
+// tile of the forward only copies 16-byte chunks.  Layout per (slice, coil):
+// [K-step s][chunk (h, m)][row y < yp][16 B], rows past ny are zero.
+__global__ __launch_bounds__(256) void k_coil_weight_bf16(const NudftTable tab) {
+    const int64_t gu = (int64_t)blockIdx.x * 256 + threadIdx.x;   // one (slice, coil, step, row) unit
+    int k = 0;
+    int64_t begin = 0;
+    for (; k < tab.nitems; ++k) {
+        const NudftItem& c = tab.it[k];
+        const int64_t u = fwd_split_units(c.nx, c.ny, c.nc, c.nb);
+        if (gu < begin + u) break;
+        begin += u;
+    }
+    if (k >= tab.nitems) return;
+    const NudftItem& it = tab.it[k];
+    const int yp = fwd_padded_rows(it.ny);
+    const int nsteps = (int)ceil_div(it.nx, KC);
+    const int i = (int)(gu - begin);
+    const int y = i % yp;
+    const int r1 = i / yp;
+    const int s = r1 % nsteps;
+    const int bg = r1 / nsteps;
+    const int g = bg % it.nc, b = bg / it.nc;
+    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
+    float2 v[KC];
+    const int64_t npix = (int64_t)it.nx * it.ny;
+    const float2* sm = it.smaps + b * it.smaps_bs + g * npix + (int64_t)y * it.nx;
+    const float2* im = it.img + b * npix + (int64_t)y * it.nx;
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        const int x = s * KC + j;
+        v[j] = (y < it.ny && x < it.nx) ? cmul(sm[x], im[x]) : make_float2(0.f, 0.f);
+    }
+    // Chunk planes of a K-step are yp rows long here (kRows in LDS).
+    char* base = reinterpret_cast<char*>(it.wimg) + (((int64_t)bg * nsteps + s) * 6 * yp) * 16;
+    PolBF16::store_a_rows(base, y, yp, v);
+}
+
+// Split-FP16 form of the pre-pass: one wave per (slice, coil, padded row).
+// The wave first finds the row's largest real or imaginary magnitude, scales
+// the row by the power of two that puts it in [2^14, 2^15), then splits and
+// packs it as k_coil_weight_bf16 does.  The inverse scale of each row is kept
+// after the operand chunks (fwd_rowscale) for the forward's epilogue.
+__global__ __launch_bounds__(256) void k_coil_weight_f16(const NudftTable tab) {
+    const int64_t gr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // one (slice, coil, row) unit
+    const int lane = threadIdx.x & 63;
+    int k = 0;
+    int64_t begin = 0;
+    for (; k < tab.nitems; ++k) {
+        const NudftItem& c = tab.it[k];
+        const int64_t u = (int64_t)c.nb * c.nc * fwd_padded_rows(c.ny);
+        if (gr < begin + u) break;
+        begin += u;
+    }
+    if (k >= tab.nitems) return;
+    const NudftItem& it = tab.it[k];
+    const int yp = fwd_padded_rows(it.ny);
+    const int nsteps = (int)ceil_div(it.nx, KC);
+    const int i = (int)(gr - begin);
+    const int y = i % yp;
+    const int bg = i / yp;
+    const int g = bg % it.nc, b = bg / it.nc;
+    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
+    const int64_t npix = (int64_t)it.nx * it.ny;
+    const int yc = y < it.ny ? y : 0;
+    const float2* sm = it.smaps + b * it.smaps_bs + g * npix + (int64_t)yc * it.nx;
+    const float2* im = it.img + b * npix + (int64_t)yc * it.nx;
+    auto row_step = [&](int s, float2 (&v)[KC]) {
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const int x = s * KC + j;
+            v[j] = (y < it.ny && x < it.nx) ? cmul(sm[x], im[x]) : make_float2(0.f, 0.f);
+        }
+    };
+    float m = 0.f;
+    for (int s = lane; s < nsteps; s += 64) {
+        float2 v[KC];
+        row_step(s, v);
+#pragma unroll
+        for (int j = 0; j < KC; ++j) m = fmaxf(m, fmaxf(fabsf(v[j].x), fabsf(v[j].y)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    const int se = split_scale_exp(m);
+    const float sc = ldexpf(1.0f, se);
+    char* wbase = reinterpret_cast<char*>(it.wimg);
+    for (int s = lane; s < nsteps; s += 64) {
+        float2 v[KC];
+        row_step(s, v);
+#pragma unroll
+        for (int j = 0; j < KC; ++j) v[j] = cscale(v[j], sc);
+        PolF16::store_a_rows(wbase + (((int64_t)bg * nsteps + s) * 6 * yp) * 16, y, yp, v);
+    }
+    if (lane == 0) fwd_rowscale(it.wimg, it.nx, it.ny, it.nc, it.nb)[(int64_t)bg * yp + y] = ldexpf(1.0f, -se);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,23 +460,46 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         const int nvalid = wrow0 >= ny ? 0 : min(nt, (ny - wrow0 + 31) / 32);
         const int yrow = y0 + tid;
         const bool row_ok = yrow < ny && tid < prows;
-        // rows past ny load row ny-1 (always in bounds) and are zeroed when staged
+        // FP32: rows past ny load row ny-1 (always in bounds) and are zeroed when
+        // staged.  Split-BF16: the pre-pass already holds zero rows up to yp.
         const float4* src = reinterpret_cast<const float4*>(wi + (int64_t)min(yrow, ny - 1) * pitch);
         const float rmask = row_ok ? 1.0f : 0.0f;
+        const int yp = fwd_padded_rows(ny);
+        const char* wsplit = reinterpret_cast<const char*>(it.wimg) +
+                             ((int64_t)(b * nc + g) * nsteps * 6 * yp + (int64_t)min(yrow, yp - 1)) * 16;
         float4 pre[KC / 2];
 
+        // FP32: global -> registers (prefetched one step ahead) -> LDS planes.
+        // Split-BF16: the pre-split chunks go global -> LDS directly
+        // (global_load_lds_dwordx4: lane i of a wave lands at base + 16 i, and the
+        // LDS chunk planes hold consecutive rows), issued one step ahead.
         auto load_a = [&](int s) {
+            if constexpr (P::kPresplitA) {
+                const int st = s & 1;
+                char* dst = sA0 + st * P::kABytes + wave * 64 * 16;   // wave-uniform
+                const char* g = wsplit + (int64_t)s * 6 * yp * 16;
 #pragma unroll
-            for (int j = 0; j < KC / 2; ++j) pre[j] = src[s * (KC / 2) + j];
+                for (int c = 0; c < 6; ++c)
+                    __builtin_amdgcn_global_load_lds(g + (int64_t)c * yp * 16, dst + c * kRows * 16, 16, 0, 0);
+            } else {
+#pragma unroll
+                for (int j = 0; j < KC / 2; ++j) pre[j] = src[s * (KC / 2) + j];
+            }
         };
         auto store_a = [&](int st) {
-            float2 v[KC];
+            if constexpr (!P::kPresplitA) {
+                float2 v[KC];
 #pragma unroll
-            for (int j = 0; j < KC / 2; ++j) {
-                v[2 * j] = make_float2(pre[j].x * rmask, pre[j].y * rmask);
-                v[2 * j + 1] = make_float2(pre[j].z * rmask, pre[j].w * rmask);
+                for (int j = 0; j < KC / 2; ++j) {
+                    v[2 * j] = make_float2(pre[j].x * rmask, pre[j].y * rmask);
+                    v[2 * j + 1] = make_float2(pre[j].z * rmask, pre[j].w * rmask);
+                }
+                P::store_a(sA0 + st * P::kABytes, tid, v);
             }
-            P::store_a(sA0 + st * P::kABytes, tid, v);
+        };
+        // LDS writes by global_load_lds complete with the vector-memory counter.
+        auto wait_a = [&]() {
+            if constexpr (P::kPresplitA) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         };
         auto store_b = [&](int st, int s) {
             float2 e0 = make_float2(0.f, 0.f), e1 = e0;
@@ -352,6 +520,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         load_a(0);
         store_a(0);
         store_b(0, 0);
+        wait_a();
         __syncthreads();
         for (int s = 0; s < nsteps; ++s) {
             const int cur = s & 1;
@@ -365,14 +534,22 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
                 store_a(cur ^ 1);
                 store_b(cur ^ 1, s + 1);
             }
+            wait_a();
             __syncthreads();
         }
 
         // Epilogue: sum_y T[y][k] Ey[k][y] over this pass's rows.  Rows of a
         // lane are ybase + 32 t + 8 q + r (r < 4); the phase is built as
         // Ey(ybase) * E(32 t) * E(8 q) * E(r) from ten accurate factors.
+        // Split-FP16: the phase scale and each row's pre-pass scale are undone
+        // here, one after the other (each factor a normal power of two).
+        constexpr float kInvB = 1.0f / P::kBScale;
         float2 part = make_float2(0.f, 0.f);
         if (e_ok && nvalid > 0) {
+            const float* rsc = nullptr;
+            if constexpr (P::kScaled)
+                rsc = fwd_rowscale(it.wimg, nx, ny, nc, it.nb) + (int64_t)(b * nc + g) * fwd_padded_rows(ny) +
+                      wrow0 + h * 4;
             const int ybase = wrow0 + h * 4 - yh;
             const float2 e0 = phase_neg(fy4, (double)ybase);
             float2 f1[4], f8[4], f32[NT];
@@ -391,11 +568,17 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const float2 etq = cmul(et, f8[q]);
+                        float4 rs4 = make_float4(1.f, 1.f, 1.f, 1.f);
+                        if constexpr (P::kScaled) rs4 = *reinterpret_cast<const float4*>(rsc + t * 32 + q * 8);
+                        const float rs[4] = {rs4.x, rs4.y, rs4.z, rs4.w};
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int i = q * 4 + r;
                             const int y = wrow0 + t * 32 + q * 8 + h * 4 + r;
-                            if (y < ny) part = cadd(part, cmul(make_float2(acc_re[t][i], acc_im[t][i]), cmul(etq, f1[r])));
+                            if (y < ny)
+                                part = cadd(part, cmul(make_float2(acc_re[t][i] * kInvB * rs[r],
+                                                                   acc_im[t][i] * kInvB * rs[r]),
+                                                       cmul(etq, f1[r])));
                         }
                     }
                 }
@@ -419,6 +602,7 @@ template <class P, int NT>
 __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + P::kBBytes)];
     __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC + 2];   // conj(Ey) for the next A (padded rows)
+    __shared__ float sUnscale[2 * kNT];                                       // split-FP16: per coil of the group
     char* const sA0 = smem;
     char* const sB0 = smem + 2 * P::kABytes;
 
@@ -472,6 +656,26 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
         const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk;
         float2 dreg[KC];
 
+        // Split-FP16: W rows of coil ac are scaled by the power of two that
+        // puts |Re d| + |Im d| (>= |Re W|, |Im W|) of this split's samples in
+        // [2^14, 2^15); the 32 threads of the coil share the scan.
+        float ascale = 1.0f;
+        if constexpr (P::kScaled) {
+            float m = 0.f;
+            for (int64_t kc = kbeg; kc < kend; kc += 8 * kAdjRows) {
+                float2 dv[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) dv[j] = drow[min(kc + ay + j * kAdjRows, kend - 1)];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) m = fmaxf(m, fabsf(dv[j].x) + fabsf(dv[j].y));
+            }
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 32));
+            const int se = split_scale_exp(m);
+            ascale = ldexpf(1.0f, se);
+            if (ay == 0 && ac < gsz) sUnscale[ac] = ldexpf(1.0f, -se);
+        }
+
         // Loads are unconditional from clamped (in-bounds) indices; samples past
         // the split end are masked when staged, so no load sits in a branch.
         auto load_d = [&](int s) {
@@ -503,7 +707,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
             if (!(bx_ok && k + 1 < kend)) e1 = make_float2(0.f, 0.f);
             P::store_b(sB0 + st * P::kBBytes, bx, bk, e0, e1);
         };
-        const float amask = a_ok ? 1.0f : 0.0f;
+        const float amask = a_ok ? ascale : 0.0f;
         auto gen_a = [&](int st, int est) {
             float2 w[KC];
 #pragma unroll
@@ -566,12 +770,17 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
                 if (t < nvalid) {
                     const int g = g0 + wm * nt + t;
                     const float2* sg = sm + (int64_t)g * npix;
+                    // split-FP16: phase scale, then this coil's data scale
+                    constexpr float kInvB = 1.0f / P::kBScale;
+                    float us = 1.0f;
+                    if constexpr (P::kScaled) us = sUnscale[wm * nt + t];
 #pragma unroll
                     for (int i = 0; i < 16; ++i) {
                         const int y = y0 + (i >> 2) * 8 + h * 4 + (i & 3);
                         if (y < ny)
                             part[i] = cadd(part[i], cmulc(sg[(int64_t)y * nx + xe],
-                                                          make_float2(acc_re[t][i], acc_im[t][i])));
+                                                          make_float2(acc_re[t][i] * kInvB * us,
+                                                                      acc_im[t][i] * kInvB * us)));
                     }
                 }
             }
@@ -601,14 +810,8 @@ int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb) {
     return (int64_t)nb * nc * ceil_div(nk, kFwdCols);
 }
 
-int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb) {
+int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb) {  // FP32 form, complex elements
     return (int64_t)nb * nc * ny * (ceil_div(nx, KC) * KC);
-}
-
-int fwd_nt(int ny) {
-    const int npass = (int)ceil_div(ny, kRows);
-    const int nt = (int)ceil_div(ny, 64 * npass);
-    return nt < 2 ? 2 : nt;
 }
 
 int adj_nt(int nc) {
@@ -644,8 +847,21 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
     *kper = (int32_t)per;
 }
 
-hipError_t launch_coil_weight(const NudftTable& t, hipStream_t s) {
+hipError_t launch_coil_weight(const NudftTable& t, int precision, hipStream_t s) {
     if (t.cw_total <= 0) return hipSuccess;
+    if (precision == MRI_BF16X3) {
+        int64_t units = 0;
+        for (int i = 0; i < t.nitems; ++i)
+            units += fwd_split_units(t.it[i].nx, t.it[i].ny, t.it[i].nc, t.it[i].nb);
+        hipLaunchKernelGGL(k_coil_weight_bf16, dim3((unsigned)ceil_div(units, 256)), dim3(256), 0, s, t);
+        return hipGetLastError();
+    }
+    if (precision == MRI_FP16X3) {
+        int64_t rows = 0;
+        for (int i = 0; i < t.nitems; ++i) rows += fwd_rowscale_floats(t.it[i].ny, t.it[i].nc, t.it[i].nb);
+        hipLaunchKernelGGL(k_coil_weight_f16, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, s, t);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(t.cw_total, 4 * 256)), dim3(256), 0, s, t);
     return hipGetLastError();
 }
@@ -699,8 +915,9 @@ hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t 
     if (t.total_tiles <= 0) return hipSuccess;
     return launch_by_nt(t, [](const NudftItem& it) { return fwd_nt(it.ny); },
                         [&](const NudftTable& sub, int nt) {
-                            return precision == MRI_BF16X3 ? fwd_variant<PolBF16>(sub, nt, s)
-                                                           : fwd_variant<PolF32>(sub, nt, s);
+                            return precision == MRI_BF16X3   ? fwd_variant<PolBF16>(sub, nt, s)
+                                   : precision == MRI_FP16X3 ? fwd_variant<PolF16>(sub, nt, s)
+                                                             : fwd_variant<PolF32>(sub, nt, s);
                         });
 }
 
@@ -708,8 +925,9 @@ hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t 
     if (t.total_tiles <= 0) return hipSuccess;
     return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); },
                         [&](const NudftTable& sub, int nt) {
-                            return precision == MRI_BF16X3 ? adj_variant<PolBF16>(sub, nt, s)
-                                                           : adj_variant<PolF32>(sub, nt, s);
+                            return precision == MRI_BF16X3   ? adj_variant<PolBF16>(sub, nt, s)
+                                   : precision == MRI_FP16X3 ? adj_variant<PolF16>(sub, nt, s)
+                                                             : adj_variant<PolF32>(sub, nt, s);
                         });
 }
 

@@ -23,7 +23,7 @@ int check_shape(const mri_shape* s) {
 
 int check_precision(int p) {
     if (p == MRI_FP32) return MRI_OK;
-    if (p == MRI_BF16X3) return MRI_OK;
+    if (p == MRI_BF16X3 || p == MRI_FP16X3) return MRI_OK;
     return MRI_EINVAL;
 }
 
@@ -38,7 +38,10 @@ int check_params(const mri_admm_params* p) {
 }
 
 size_t forward_ws(const mri_shape& s) {
-    return ws_align(sizeof(float2) * (size_t)fwd_wimg_elems(s.nx, s.ny, s.ncoils, s.batch));
+    const size_t f32 = sizeof(float2) * (size_t)fwd_wimg_elems(s.nx, s.ny, s.ncoils, s.batch);
+    const size_t bf = 96 * (size_t)fwd_split_units(s.nx, s.ny, s.ncoils, s.batch) +
+                      sizeof(float) * (size_t)fwd_rowscale_floats(s.ny, s.ncoils, s.batch);
+    return ws_align(f32 > bf ? f32 : bf);
 }
 
 size_t adjoint_ws(const mri_shape& s) {
@@ -165,7 +168,8 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         const int64_t ft = fwd_tiles(sh.nx, sh.ny, sh.ncoils, sh.nk, sh.batch);
         const int64_t at_ = adj_tiles_per_split(sh.nx, sh.ny, sh.batch) * L.ksplit;
         const int64_t cw = fwd_wimg_elems(sh.nx, sh.ny, sh.ncoils, sh.batch);
-        if (cw >= ((int64_t)1 << 31)) return MRI_ENOTSUP;     // 32-bit indexing inside an item
+        if (cw >= ((int64_t)1 << 31) || fwd_split_units(sh.nx, sh.ny, sh.ncoils, sh.batch) >= ((int64_t)1 << 31))
+            return MRI_ENOTSUP;     // 32-bit indexing inside an item
         tiles_f += ft;
         tiles_a += at_;
 
@@ -210,13 +214,13 @@ hipError_t enqueue_init(const Plan& p, hipStream_t s) {
 hipError_t enqueue_iteration(const Plan& p, hipStream_t s) {
     PLAN_TRY(launch_mu(p.st, s));
     PLAN_TRY(launch_rhs(p.st, s));
-    PLAN_TRY(launch_coil_weight(p.finit, s));
+    PLAN_TRY(launch_coil_weight(p.finit, p.precision, s));
     PLAN_TRY(launch_nudft_forward(p.finit, p.precision, s));
     PLAN_TRY(launch_nudft_adjoint(p.ainit, p.precision, s));
     PLAN_TRY(launch_adj_finish(p.st, kFinishCgInit, s));
     PLAN_TRY(launch_finalize(p.st, kFinCgInit, s));
     for (int j = 0; j < p.max_cg; ++j) {
-        PLAN_TRY(launch_coil_weight(p.fstep, s));
+        PLAN_TRY(launch_coil_weight(p.fstep, p.precision, s));
         PLAN_TRY(launch_nudft_forward(p.fstep, p.precision, s));
         PLAN_TRY(launch_nudft_adjoint(p.astep, p.precision, s));
         PLAN_TRY(launch_adj_finish(p.st, kFinishCgStep, s));

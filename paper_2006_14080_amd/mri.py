@@ -24,7 +24,9 @@ LIB_PATH = os.path.join(_HERE, "libmriadmm.so")
 
 FP32 = 0
 BF16X3 = 1
-PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3}
+FP16X3 = 2
+PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
+PRECISION_NAMES = {v: k for k, v in PRECISIONS.items()}
 
 OP_FORWARD, OP_ADJOINT, OP_ADMM = 0, 1, 2
 

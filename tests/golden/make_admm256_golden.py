@@ -5,8 +5,9 @@
 Calls only the oracle and the seeded input generators: data = oracle F(phantom)
 + noise (rounded to complex64, as the GPU receives it), then the oracle's ADMM
 with the workload's parameters (30 ADMM x 5 CG, lambda 1e-3, beta 1).  Writes
-admm256_oracle.npz (the complex64 image and the solve's counters).  Takes a
-few minutes on 8 cores.
+admm256_oracle.npz: the k-space data it solved for (complex64 [coils][nk]),
+the complex64 image and the solve's counters.  Takes about 12 minutes on 8
+cores.
 """
 import os
 import sys
@@ -29,7 +30,7 @@ def main():
     res = admm.admm(data, p.smaps, p.traj, wl.lam, wl.beta, wl.admm_iters, wl.cg_iters)
     dt = time.time() - t0
     out = os.path.join(HERE, "admm256_oracle.npz")
-    np.savez_compressed(out, image=res.image.astype(np.complex64), admm_iters=res.admm_iters,
+    np.savez_compressed(out, data=data, image=res.image.astype(np.complex64), admm_iters=res.admm_iters,
                         cg_steps=res.cg_steps, alpha=res.alpha, tau=res.tau, seconds=dt)
     print(f"wrote {out}: {res.admm_iters} ADMM, {res.cg_steps} CG steps, {dt:.0f} s")
 

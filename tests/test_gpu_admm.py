@@ -1,5 +1,7 @@
 """GPU parity of admm_solve (Alg. 4 with CG of Alg. 2) against the FP64
 oracle, through the C ABI.  Bar: final-image NRMSE <= 1e-4."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -40,7 +42,7 @@ def _oracle(p, data, b, lam, beta, na, nc, **kw):
     return oadmm.admm(data[b], p.smaps, p.traj, lam, beta, na, nc, **kw)
 
 
-@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3])
+@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3, mri.FP16X3])
 def test_admm32_full_counts(prec):
     # FP32: the plain 32x32 workload; BF16X3: its split-BF16 precision form.
     wl = synth.ADMM32
@@ -103,7 +105,7 @@ def test_tolerances_stop_on_device():
     assert nrmse(img[0], ref.image) <= NRMSE
 
 
-@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3])
+@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3, mri.FP16X3])
 def test_admm256_shape_reduced_counts(prec):
     # The 256x256, 8-coil, 64x512-sample launch configuration of the benchmark,
     # with 2 ADMM x 2 CG steps so the oracle finishes in seconds.
@@ -114,3 +116,37 @@ def test_admm256_shape_reduced_counts(prec):
     ref = _oracle(p, data, 0, wl.lam, wl.beta, 2, 2)
     assert st[0]["admm_iters"] == 2 and st[0]["cg_steps"] == 4
     assert nrmse(img[0], ref.image) <= NRMSE
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "admm256_oracle.npz")
+
+
+def _admm256_full(prec):
+    # The whole benchmark solve (256x256, 8 coils, 64x512 samples, 30 ADMM x
+    # 5 CG) on the data stored with the oracle's own 30 x 5 reconstruction
+    # (tests/golden/make_admm256_golden.py; the oracle takes minutes here).
+    wl = synth.ADMM256
+    g = np.load(GOLDEN)
+    p = synth.make_problem(wl)
+    img, st = _solve(p, g["data"][None], mri.AdmmParams(wl.lam, wl.beta, wl.admm_iters, wl.cg_iters,
+                                                        precision=prec))
+    assert st[0]["status"] == 0
+    assert st[0]["admm_iters"] == int(g["admm_iters"]) == 30
+    assert st[0]["cg_steps"] == int(g["cg_steps"]) == 150
+    e = nrmse(img[0], g["image"])
+    print(f"{mri.PRECISION_NAMES[prec]}: image NRMSE vs stored oracle = {e:.3e}")
+    return e
+
+
+@pytest.mark.parametrize("prec", [mri.FP32, mri.FP16X3])
+def test_admm256_full_counts_against_stored_oracle(prec):
+    assert _admm256_full(prec) <= NRMSE
+
+
+def test_admm256_full_counts_bf16x3_reported_error():
+    # The bf16 split keeps ~16 bits per operand (per-operator error ~4e-6);
+    # 150 CG steps carry that to an image NRMSE of about 3e-3 on this problem,
+    # above the 1e-4 bar that FP32 and FP16x3 meet.  Held here to its
+    # measured size so a regression shows.
+    e = _admm256_full(mri.BF16X3)
+    assert 1e-4 < e <= 1e-2

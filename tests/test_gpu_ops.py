@@ -2,8 +2,10 @@
 against the FP64 oracle, through the C ABI.
 
 Bar: relative L2 error <= 1e-5 per NUDFT (element by element over the whole
-output), in FP32 and in the split-BF16 (BF16x3) form; TV transforms are exact
-up to one FP32 rounding per element.
+output), in FP32 and in the split forms (BF16x3, FP16x3); TV transforms are
+exact up to one FP32 rounding per element.  The FP16x3 form is also held to
+1e-6 and checked over extreme input scales (its operands are rescaled by
+powers of two into fp16's range).
 Sizes span several tiles (64 samples / 256 rows for the forward, 64 x 32
 pixels and 8-coil groups for the adjoint) with ragged tails; full-size
 shapes are checked on sampled outputs that the oracle computes one by one.
@@ -58,7 +60,7 @@ SHAPES = [
 ]
 
 
-PRECS = [mri.FP32, mri.BF16X3]
+PRECS = [mri.FP32, mri.BF16X3, mri.FP16X3]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -147,6 +149,59 @@ def test_full_size_sampled(wl, batch, prec):
         rows[:2], cols[:2] = [0, wl.ny - 1], [wl.nx - 1, 0]
         ref = onudft.adjoint_pixels(dat[b], p.smaps, p.traj, rows, cols)
         assert rel(a[b][rows, cols], ref) <= TOL
+
+
+def test_split_forms_error_ordering():
+    # Per-operator error of each form on one mid-size problem.  The bf16 split
+    # keeps ~16 bits per operand and its product error dominates; the fp16
+    # split keeps ~22, below FP32 accumulation's own rounding, so FP16x3 lands
+    # at the FP32 form's error.
+    nx, ny, nc, nk = 80, 72, 5, 2500
+    img, sm, tr, dat = _inputs(nx, ny, nc, nk, 1, 90)
+    fref = onudft.forward(img[0], sm, tr)
+    aref = onudft.adjoint(dat[0], sm, tr)
+    err = {}
+    for prec in PRECS:
+        f = mri.nudft_forward(_gpu(img), _gpu(sm), _gpu(tr), precision=prec).cpu().numpy()[0]
+        a = mri.nudft_adjoint(_gpu(dat), _gpu(sm), _gpu(tr), ny, nx, precision=prec).cpu().numpy()[0]
+        err[prec] = (rel(f, fref), rel(a, aref))
+    print("relative error (forward, adjoint):", {mri.PRECISION_NAMES[p]: e for p, e in err.items()})
+    for k in range(2):
+        assert err[mri.FP16X3][k] <= 1e-6
+        assert err[mri.FP16X3][k] * 4 <= err[mri.BF16X3][k]
+        assert err[mri.FP16X3][k] <= 2 * err[mri.FP32][k] + 1e-7
+
+
+@pytest.mark.parametrize("scale", [1e-30, 1e-8, 1e8, 1e30])
+def test_fp16x3_extreme_scales(scale):
+    # Row and coil scales follow the data: the relative error does not depend
+    # on the magnitude of the inputs, down to FP32's small normal numbers and
+    # up to its large ones.  Rows of the image also span 12 decades.
+    nx, ny, nc, nk = 40, 36, 3, 600
+    img, sm, tr, dat = _inputs(nx, ny, nc, nk, 1, 95)
+    img = (img * (10.0 ** ((np.arange(ny) % 13) - 6))[None, :, None]).astype(np.complex64)
+    img = (img * np.float32(scale)).astype(np.complex64)
+    dat = (dat * np.float32(scale)).astype(np.complex64)
+    f = mri.nudft_forward(_gpu(img), _gpu(sm), _gpu(tr), precision=mri.FP16X3).cpu().numpy()[0]
+    a = mri.nudft_adjoint(_gpu(dat), _gpu(sm), _gpu(tr), ny, nx, precision=mri.FP16X3).cpu().numpy()[0]
+    assert np.isfinite(f).all() and np.isfinite(a).all()
+    assert rel(f, onudft.forward(img[0], sm, tr)) <= 1e-6
+    assert rel(a, onudft.adjoint(dat[0], sm, tr)) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_zero_and_nonfinite_inputs(prec):
+    nx, ny, nc, nk = 24, 20, 2, 300
+    img, sm, tr, dat = _inputs(nx, ny, nc, nk, 1, 97)
+    z = mri.nudft_forward(_gpu(np.zeros_like(img)), _gpu(sm), _gpu(tr), precision=prec).cpu().numpy()
+    za = mri.nudft_adjoint(_gpu(np.zeros_like(dat)), _gpu(sm), _gpu(tr), ny, nx, precision=prec).cpu().numpy()
+    assert not z.any() and not za.any()
+    # a NaN in the input reaches the output (the solver's status check relies on it)
+    img[0, 3, 5] = np.nan
+    dat[0, 1, 7] = np.nan
+    f = mri.nudft_forward(_gpu(img), _gpu(sm), _gpu(tr), precision=prec).cpu().numpy()
+    a = mri.nudft_adjoint(_gpu(dat), _gpu(sm), _gpu(tr), ny, nx, precision=prec).cpu().numpy()
+    assert np.isnan(f).any() and np.isnan(a).any()
 
 
 @pytest.mark.parametrize("nx,ny,batch", [(32, 32, 1), (7, 5, 3), (1, 9, 2), (300, 2, 1)])
