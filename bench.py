@@ -13,7 +13,10 @@ steps.  Also reported:
   events on the stream it runs on, against the MI355X dense FP32 MFMA peak
   (BF16 / FP16 peak for the split forms, where each product costs three);
 * cpu_baseline -- the FP64 NumPy oracle timed on the host on a bounded sample
-  (one ADMM iteration with 5 CG steps of the same problem).
+  (one ADMM iteration with 5 CG steps of the same problem);
+* image_nrmse_vs_oracle -- the timed solve's image against the oracle's own
+  30 x 5 reconstruction of the same data (stored under tests/golden), so the
+  forms (fp32, bf16x3, fp16x3) are compared at their accuracy.
 
 Other workloads (one JSON line each):
 
@@ -38,6 +41,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6}   # MI355X dense MFMA peaks
 DTYPE = {"fp32": "f32", "bf16x3": "bf16x3", "fp16x3": "f16x3"}
+# Oracle data and 30 x 5 reconstruction of the 256x256 problem
+# (written by tests/golden/make_admm256_golden.py).
+GOLDEN_ADMM256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "admm256_oracle.npz")
 HBM_PEAK_GBS = 8000.0
 
 
@@ -187,9 +193,16 @@ def main():
     dev = torch.device("cuda:0")
     g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     sm, tr, truth = g(p.smaps), g(p.traj), g(p.truth)
-    # Synthetic k-space data: F(phantom) on the GPU plus seeded complex noise.
-    data = mri.nudft_forward(truth, sm, tr, precision=mri.FP32)
-    data += g(p.noise.astype(np.complex64))
+    # Synthetic k-space data F(phantom) + seeded complex noise: the copy stored
+    # beside the oracle's own 30 x 5 reconstruction of this problem when it is
+    # there (so the final image can be compared with it), else formed on the GPU.
+    golden = None
+    if os.path.exists(GOLDEN_ADMM256):
+        golden = np.load(GOLDEN_ADMM256)
+        data = g(golden["data"][None])
+    else:
+        data = mri.nudft_forward(truth, sm, tr, precision=mri.FP32)
+        data += g(p.noise.astype(np.complex64))
     torch.cuda.synchronize()
 
     params = mri.AdmmParams(wl.lam, wl.beta, wl.admm_iters, wl.cg_iters, precision=prec)
@@ -215,6 +228,11 @@ def main():
     if st["status"] != 0 or st["admm_iters"] != wl.admm_iters:
         raise RuntimeError(f"solve did not run to completion: {st}")
     iters_per_s = wl.admm_iters * args.steps / (ms_total / 1e3)
+    nrmse = None
+    if golden is not None:
+        ref = golden["image"].astype(np.complex128)
+        got = out[0].cpu().numpy().astype(np.complex128)
+        nrmse = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
     # Per-kernel timing of the two NUDFT operators at the solve's launch
     # configuration (same kernels, tables and stream as inside admm_solve).
@@ -281,6 +299,7 @@ def main():
                        "fp32_equiv_tflops": {"nudft_forward": flop / fwd_ms / 1e9,
                                              "nudft_adjoint": flop / adj_ms / 1e9}},
         "wall_s_timed": wall,
+        "image_nrmse_vs_oracle": nrmse,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, p)

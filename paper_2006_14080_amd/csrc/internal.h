@@ -81,9 +81,25 @@ __host__ __device__ inline int64_t fwd_rowscale_floats(int ny, int nc, int nb) {
 __host__ __device__ inline float* fwd_rowscale(float2* wimg, int nx, int ny, int nc, int nb) {
     return reinterpret_cast<float*>(reinterpret_cast<char*>(wimg) + 96 * fwd_split_units(nx, ny, nc, nb));
 }
-int adj_nt(int nc);
+// Row tiles per wave of the adjoint: coils run in even groups of 2 * adj_nt.
+__host__ __device__ inline int adj_nt(int nc) {
+    const int ngroups = (nc + kAdjCoilGroup - 1) / kAdjCoilGroup;
+    const int gsz = (nc + ngroups - 1) / ngroups;
+    const int nt = (gsz + 1) / 2;
+    return nt < 2 ? 2 : nt;
+}
 // Partial images the adjoint writes per slice: one per (sample split, coil group).
-int adj_partial_planes(int nc, int ksplit);
+__host__ __device__ inline int adj_partial_planes(int nc, int ksplit) {
+    return ksplit * ((nc + 2 * adj_nt(nc) - 1) / (2 * adj_nt(nc)));
+}
+// Adjoint workspace: the partial images [planes][nb][ny][nx], then (split-FP16
+// form) one int32 scale exponent per (slice, coil, sample split).
+__host__ __device__ inline int64_t adj_partial_elems(int nx, int ny, int nc, int nb, int ksplit) {
+    return (int64_t)adj_partial_planes(nc, ksplit) * nb * nx * ny;
+}
+__host__ __device__ inline int32_t* adj_scale_exp(float2* part, int nx, int ny, int nc, int nb, int ksplit) {
+    return reinterpret_cast<int32_t*>(part + adj_partial_elems(nx, ny, nc, nb, ksplit));
+}
 // Choose the sample-range split of the adjoint for one problem.
 void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
                int32_t* ksplit, int32_t* kper);

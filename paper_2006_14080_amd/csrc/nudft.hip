@@ -116,11 +116,12 @@ struct PolF32 {
 // a 16-bit type T; a real product a b is formed as hi_a hi_b + hi_a lo_b +
 // lo_a hi_b with FP32 accumulation.  v_mfma_f32_32x32x16_{bf16,f16} take 8
 // K-slots per lane half; the six products of a complex K value for one
-// accumulator occupy six slots:
-//   A    : [ArH, ArH, ArL, AiH, AiH, AiL]
-//   B_re : [BrH, BrL, BrH, -BiH, -BiL, -BiH]   -> Ar Br - Ai Bi
-//   B_im : [BiH, BiL, BiH, BrH, BrL, BrH]      -> Ar Bi + Ai Br
-// Lane half h takes complex K values 4h..4h+3 (24 slots = 3 instructions),
+// accumulator occupy six slots, ordered so that every 32-bit word is one
+// converted (re, im) pair and needs no repacking:
+//   A    : [ArH, AiH | ArL, AiL | ArH, AiH]
+//   B_re : [BrH, -BiH | BrH, -BiH | BrL, -BiL]   -> Ar Br - Ai Bi
+//   B_im : [BiH, BrH | BiH, BrH | BiL, BrL]      -> Ar Bi + Ai Br
+// Lane half h takes complex K values 4h..4h+3 (12 words = 3 instructions),
 // so 8 complex K values cost 3 MFMAs per accumulator with no idle slot.
 // LDS keeps every 16-byte operand chunk ready: A [h][m][row], B [var][h][m][col].
 //
@@ -137,7 +138,9 @@ struct PolF32 {
 template <class T, bool Scaled>
 struct PolSplit {
     typedef T vec8 __attribute__((ext_vector_type(8)));
-    typedef T vec4 __attribute__((ext_vector_type(4)));
+    typedef T vec2 __attribute__((ext_vector_type(2)));
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     static constexpr bool kPrioritiseMfma = true;    // measured: +5% on the VALU-heavy forward
     static constexpr bool kPresplitA = true;         // forward A pre-split into operand chunks once per call
     static constexpr bool kScaled = Scaled;
@@ -145,24 +148,32 @@ struct PolSplit {
     static constexpr int kABytes = 2 * 3 * kRows * 16;
     static constexpr int kBBytes = 2 * 2 * 3 * 64 * 16;
 
-    struct Sp {
-        T h, l;
+    // (hi, lo) words of the pair (a, b): hi = [T(a), T(b)], lo = [T(a - hi_a), T(b - hi_b)].
+    struct Words {
+        uint32_t hi, lo;
     };
-    __device__ __forceinline__ static Sp split(float a) {
-        Sp s;
-        s.h = static_cast<T>(a);
-        s.l = static_cast<T>(a - static_cast<float>(s.h));
-        return s;
+    __device__ __forceinline__ static Words split2(float a, float b) {
+        const vec2 h = {static_cast<T>(a), static_cast<T>(b)};
+        uint32_t hw = __builtin_bit_cast(uint32_t, h);
+        float ha, hb;
+        if constexpr (__is_same(T, __bf16)) {
+            // A bf16 is the top half of an FP32: read both back from the packed
+            // word.  The conversion is written as the instruction itself so the
+            // compiler keeps the one packed result instead of converting each
+            // half again.
+            asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(hw) : "v"(a), "v"(b));
+            ha = __builtin_bit_cast(float, hw << 16);
+            hb = __builtin_bit_cast(float, hw & 0xffff0000u);
+        } else {
+            ha = static_cast<float>(h.x);
+            hb = static_cast<float>(h.y);
+        }
+        const vec2 l = {static_cast<T>(a - ha), static_cast<T>(b - hb)};
+        return {hw, __builtin_bit_cast(uint32_t, l)};
     }
-    // slot value of term t (0..5) for the A operand
-    __device__ __forceinline__ static T a_term(int t, Sp r, Sp i) {
-        return t == 0 || t == 1 ? r.h : t == 2 ? r.l : t == 5 ? i.l : i.h;
-    }
-    __device__ __forceinline__ static T bre_term(int t, Sp r, Sp i) {
-        return t == 0 || t == 2 ? r.h : t == 1 ? r.l : t == 4 ? -i.l : -i.h;
-    }
-    __device__ __forceinline__ static T bim_term(int t, Sp r, Sp i) {
-        return t == 0 || t == 2 ? i.h : t == 1 ? i.l : t == 4 ? r.l : r.h;
+    // [x, y] -> [-y, x] on the two 16-bit halves (swap, then negate the low half).
+    __device__ __forceinline__ static uint32_t rot(uint32_t w) {
+        return ((w >> 16) | (w << 16)) ^ 0x8000u;
     }
     __device__ __forceinline__ static floatx16 mfma(vec8 a, vec8 b, floatx16 c);
 
@@ -171,60 +182,44 @@ struct PolSplit {
     __device__ __forceinline__ static void store_a_rows(char* st, int row, int rows, const float2 (&v)[KC]) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            Sp r[4], i[4];
+            uint32_t w[12];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                r[q] = split(v[4 * h + q].x);
-                i[q] = split(v[4 * h + q].y);
+                const Words p = split2(v[4 * h + q].x, v[4 * h + q].y);
+                w[3 * q] = p.hi;
+                w[3 * q + 1] = p.lo;
+                w[3 * q + 2] = p.hi;
             }
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                vec8 c;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int slot = 8 * m + j, q = slot / 6, t = slot % 6;
-                    c[j] = a_term(t, r[q], i[q]);
-                }
-                *reinterpret_cast<vec8*>(st + ((int64_t)(h * 3 + m) * rows + row) * 16) = c;
+                const u32x4 c = {w[4 * m], w[4 * m + 1], w[4 * m + 2], w[4 * m + 3]};
+                *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 3 + m) * rows + row) * 16) = c;
             }
         }
     }
     __device__ __forceinline__ static void store_a(char* st, int row, const float2 (&v)[KC]) {
         store_a_rows(st, row, kRows, v);
     }
+    // B column col, complex K values kp and kp+1 (kp even): six words of each
+    // variant, i.e. words 3(kp&3) .. 3(kp&3)+5 of the half's twelve.
     __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
         const int h = kp >> 2;
-        const Sp r0 = split(e0.x * kBScale), i0 = split(e0.y * kBScale);
-        const Sp r1 = split(e1.x * kBScale), i1 = split(e1.y * kBScale);
+        const Words r0 = split2(e0.x * kBScale, -e0.y * kBScale);   // [Br, -Bi]
+        const Words r1 = split2(e1.x * kBScale, -e1.y * kBScale);
+        const uint32_t wre[6] = {r0.hi, r0.hi, r0.lo, r1.hi, r1.hi, r1.lo};
+        const uint32_t wim[6] = {rot(r0.hi), rot(r0.hi), rot(r0.lo), rot(r1.hi), rot(r1.hi), rot(r1.lo)};
 #pragma unroll
         for (int var = 0; var < 2; ++var) {
-            T sl[12];
-#pragma unroll
-            for (int t = 0; t < 6; ++t) {
-                sl[t] = var == 0 ? bre_term(t, r0, i0) : bim_term(t, r0, i0);
-                sl[6 + t] = var == 0 ? bre_term(t, r1, i1) : bim_term(t, r1, i1);
-            }
+            const uint32_t* w = var == 0 ? wre : wim;
             char* base = st + (((var * 2 + h) * 3) * 64 + col) * 16;
             if ((kp & 3) == 0) {
-                // slots 0..11: chunk 0 whole, first half of chunk 1
-                vec8 c0;
-                vec4 c1;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) c0[j] = sl[j];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) c1[j] = sl[8 + j];
-                *reinterpret_cast<vec8*>(base) = c0;
-                *reinterpret_cast<vec4*>(base + 64 * 16) = c1;
+                // words 0..5: chunk 0 whole, first half of chunk 1
+                *reinterpret_cast<u32x4*>(base) = u32x4{w[0], w[1], w[2], w[3]};
+                *reinterpret_cast<u32x2*>(base + 64 * 16) = u32x2{w[4], w[5]};
             } else {
-                // slots 12..23: second half of chunk 1, chunk 2 whole
-                vec4 c1;
-                vec8 c2;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) c1[j] = sl[j];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) c2[j] = sl[4 + j];
-                *reinterpret_cast<vec4*>(base + 64 * 16 + 8) = c1;
-                *reinterpret_cast<vec8*>(base + 2 * 64 * 16) = c2;
+                // words 6..11: second half of chunk 1, chunk 2 whole
+                *reinterpret_cast<u32x2*>(base + 64 * 16 + 8) = u32x2{w[0], w[1]};
+                *reinterpret_cast<u32x4*>(base + 2 * 64 * 16) = u32x4{w[2], w[3], w[4], w[5]};
             }
         }
     }
@@ -404,6 +399,43 @@ __global__ __launch_bounds__(256) void k_coil_weight_f16(const NudftTable tab) {
         PolF16::store_a_rows(wbase + (((int64_t)bg * nsteps + s) * 6 * yp) * 16, y, yp, v);
     }
     if (lane == 0) fwd_rowscale(it.wimg, it.nx, it.ny, it.nc, it.nb)[(int64_t)bg * yp + y] = ldexpf(1.0f, -se);
+}
+
+// Split-FP16 adjoint: scale exponent of each (slice, coil, sample split),
+// from the largest |Re d| + |Im d| (>= |Re W|, |Im W| for W = d conj(Ey)) of
+// the split's samples; one block per unit.
+__global__ __launch_bounds__(256) void k_adj_scale(const NudftTable tab) {
+    __shared__ float wmax[4];
+    int64_t u = blockIdx.x;
+    int k = 0;
+    for (; k < tab.nitems; ++k) {
+        const NudftItem& c = tab.it[k];
+        const int64_t n = (int64_t)c.nb * c.nc * c.ksplit;
+        if (u < n) break;
+        u -= n;
+    }
+    if (k >= tab.nitems) return;
+    const NudftItem& it = tab.it[k];
+    const int sp = (int)(u % it.ksplit);
+    const int64_t bg = u / it.ksplit;
+    const int b = (int)(bg / it.nc);
+    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
+    const int64_t kbeg = (int64_t)sp * it.kper;
+    const int64_t kend = min(it.nk, kbeg + it.kper);
+    const float2* d = it.data + bg * it.nk;
+    float m = 0.f;
+    for (int64_t kk = kbeg + threadIdx.x; kk < kend; kk += 256) {
+        const float2 v = d[kk];
+        m = fmaxf(m, fabsf(v.x) + fabsf(v.y));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        adj_scale_exp(it.part, it.nx, it.ny, it.nc, it.nb, it.ksplit)[bg * it.ksplit + sp] = split_scale_exp(m);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -610,14 +642,16 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     const NudftItem& it = tab.it[find_item(tab, tile)];
     const int nx = it.nx, ny = it.ny, nc = it.nc;
     const int64_t nk = it.nk;
+    // Sample splits vary fastest: the splits of one pixel tile run as
+    // neighbours on one XCD and share its L2 for the coil maps they all read.
     int local = tile - it.tile_begin;
     const int nxb = (nx + kAdjCols - 1) / kAdjCols, nyb = (ny + kAdjRows - 1) / kAdjRows;
+    const int sp = local % it.ksplit;
+    local /= it.ksplit;
     const int xb = local % nxb;
     local /= nxb;
     const int yb = local % nyb;
-    local /= nyb;
-    const int sp = local % it.ksplit;
-    const int b = local / it.ksplit;
+    const int b = local / nyb;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -632,6 +666,10 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     const int64_t kbeg = (int64_t)sp * it.kper;
     const int64_t kend = min(nk, kbeg + it.kper);
     const int nsteps = (int)ceil_div(kend - kbeg, KC);
+    const int klast = (int)(kend - kbeg - 1);             // last sample of the split, relative
+    const double* trs = traj + 2 * kbeg;
+    const int32_t* aexp = nullptr;
+    if constexpr (P::kScaled) aexp = adj_scale_exp(it.part, nx, ny, nc, it.nb, it.ksplit);
 
     // Producer roles.
     const int ey = tid & 31, ek = tid >> 5;              // E: (y, k)
@@ -652,69 +690,76 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     for (int gi = 0, g0 = 0; g0 < nc; ++gi, g0 += gsz) {
         const int ncg = min(gsz, nc - g0);
         const int nvalid = max(0, min(nt, ncg - wm * nt));
+        // Rows of coils past the group's end (a_ok false) read coil g0 and
+        // feed only accumulator tiles that the epilogue never reads.
         const bool a_ok = ac < ncg;
-        const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk;
+        const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk + kbeg;
         float2 dreg[KC];
 
-        // Split-FP16: W rows of coil ac are scaled by the power of two that
-        // puts |Re d| + |Im d| (>= |Re W|, |Im W|) of this split's samples in
-        // [2^14, 2^15); the 32 threads of the coil share the scan.
+        // Split-FP16: W rows of coil ac carry the scale k_adj_scale chose for
+        // this coil and sample split.
         float ascale = 1.0f;
         if constexpr (P::kScaled) {
-            float m = 0.f;
-            for (int64_t kc = kbeg; kc < kend; kc += 8 * kAdjRows) {
-                float2 dv[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) dv[j] = drow[min(kc + ay + j * kAdjRows, kend - 1)];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) m = fmaxf(m, fabsf(dv[j].x) + fabsf(dv[j].y));
-            }
-#pragma unroll
-            for (int off = 16; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 32));
-            const int se = split_scale_exp(m);
+            const int se = a_ok ? aexp[((int64_t)b * nc + g0 + ac) * it.ksplit + sp] : 0;
             ascale = ldexpf(1.0f, se);
             if (ay == 0 && ac < gsz) sUnscale[ac] = ldexpf(1.0f, -se);
         }
 
         // Loads are unconditional from clamped (in-bounds) indices; samples past
         // the split end are masked when staged, so no load sits in a branch.
+        // Sample indices relative to the split start fit in 32 bits.  Steps
+        // wholly inside the split load straight (one address, immediate
+        // offsets); the last step clamps to the split's last sample.
         auto load_d = [&](int s) {
-            const int64_t kb0 = kbeg + (int64_t)s * KC;
+            if (s * KC + KC - 1 <= klast) {
+                const float2* p = drow + s * KC;
 #pragma unroll
-            for (int j = 0; j < KC; ++j) dreg[j] = drow[min(kb0 + j, kend - 1)];
+                for (int j = 0; j < KC; ++j) dreg[j] = p[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < KC; ++j) dreg[j] = drow[min(s * KC + j, klast)];
+            }
         };
         // Trajectory values are prefetched one step ahead of their use:
         // tfx0/tfx1 for the next B stage, tfy for the E tile after that.
         double tfx0, tfx1, tfy;
         auto load_fx = [&](int s) {
-            const int64_t k = kbeg + (int64_t)s * KC + bk;
-            tfx0 = traj[2 * min(k, kend - 1)];
-            tfx1 = traj[2 * min(k + 1, kend - 1)];
+            const int k = s * KC + bk;
+            if (s * KC + KC - 1 <= klast) {
+                const double* q = trs + 2 * k;       // (x, y) of k, then of k + 1
+                tfx0 = q[0];
+                tfx1 = q[2];
+            } else {
+                tfx0 = trs[2 * min(k, klast)];
+                tfx1 = trs[2 * min(k + 1, klast)];
+            }
         };
         auto load_fy = [&](int s) {
-            tfy = traj[2 * min(kbeg + (int64_t)s * KC + ek, kend - 1) + 1];
+            tfy = trs[2 * min(s * KC + ek, klast) + 1];
         };
         auto gen_e = [&](int st, int s) {
-            const int64_t k = kbeg + (int64_t)s * KC + ek;
             float2 e = phase_pos(tfy * kQuarterTurnsPerRad, yr);
-            if (!(ey_ok && k < kend)) e = make_float2(0.f, 0.f);
+            if (!(ey_ok && s * KC + ek <= klast)) e = make_float2(0.f, 0.f);
             sE[st][ey][ek] = e;
         };
         auto gen_b = [&](int st, int s) {
-            const int64_t k = kbeg + (int64_t)s * KC + bk;
+            const int k = s * KC + bk;
             float2 e0 = phase_pos(tfx0 * kQuarterTurnsPerRad, xr), e1 = phase_pos(tfx1 * kQuarterTurnsPerRad, xr);
-            if (!(bx_ok && k < kend)) e0 = make_float2(0.f, 0.f);
-            if (!(bx_ok && k + 1 < kend)) e1 = make_float2(0.f, 0.f);
+            if (!(bx_ok && k <= klast)) e0 = make_float2(0.f, 0.f);
+            if (!(bx_ok && k + 1 <= klast)) e1 = make_float2(0.f, 0.f);
             P::store_b(sB0 + st * P::kBBytes, bx, bk, e0, e1);
         };
-        const float amask = a_ok ? ascale : 0.0f;
         auto gen_a = [&](int st, int est) {
             float2 w[KC];
 #pragma unroll
             for (int j = 0; j < KC; j += 2) {
                 const float4 e2 = *reinterpret_cast<const float4*>(&sE[est][ay][j]);
-                w[j] = cscale(cmul(dreg[j], make_float2(e2.x, e2.y)), amask);
-                w[j + 1] = cscale(cmul(dreg[j + 1], make_float2(e2.z, e2.w)), amask);
+                w[j] = cmul(dreg[j], make_float2(e2.x, e2.y));
+                w[j + 1] = cmul(dreg[j + 1], make_float2(e2.z, e2.w));
+                if constexpr (P::kScaled) {
+                    w[j] = cscale(w[j], ascale);
+                    w[j + 1] = cscale(w[j + 1], ascale);
+                }
             }
             P::store_a(sA0 + st * P::kABytes, ac * 32 + ay, w);
         };
@@ -812,17 +857,6 @@ int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb) {
 
 int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb) {  // FP32 form, complex elements
     return (int64_t)nb * nc * ny * (ceil_div(nx, KC) * KC);
-}
-
-int adj_nt(int nc) {
-    const int ngroups = (int)ceil_div(nc, kAdjCoilGroup);
-    const int gsz = (int)ceil_div(nc, ngroups);
-    const int nt = (gsz + 1) / 2;
-    return nt < 2 ? 2 : nt;
-}
-
-int adj_partial_planes(int nc, int ksplit) {
-    return ksplit * (int)ceil_div(nc, 2 * adj_nt(nc));
 }
 
 int64_t adj_tiles_per_split(int nx, int ny, int nb) {
@@ -923,6 +957,13 @@ hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t 
 
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s) {
     if (t.total_tiles <= 0) return hipSuccess;
+    if (precision == MRI_FP16X3) {
+        int64_t units = 0;
+        for (int i = 0; i < t.nitems; ++i) units += (int64_t)t.it[i].nb * t.it[i].nc * t.it[i].ksplit;
+        hipLaunchKernelGGL(k_adj_scale, dim3((unsigned)units), dim3(256), 0, s, t);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); },
                         [&](const NudftTable& sub, int nt) {
                             return precision == MRI_BF16X3   ? adj_variant<PolBF16>(sub, nt, s)

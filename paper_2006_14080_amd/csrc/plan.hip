@@ -47,7 +47,8 @@ size_t forward_ws(const mri_shape& s) {
 size_t adjoint_ws(const mri_shape& s) {
     int32_t ks, kp;
     adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, MRI_FP32, &ks, &kp);
-    return ws_align(sizeof(float2) * (size_t)s.nx * s.ny * s.batch * adj_partial_planes(s.ncoils, ks));
+    return ws_align(sizeof(float2) * (size_t)adj_partial_elems(s.nx, s.ny, s.ncoils, s.batch, ks) +
+                    sizeof(int32_t) * (size_t)s.batch * s.ncoils * ks);
 }
 
 AdmmLayout admm_layout(const mri_shape& s, int precision) {

@@ -20,7 +20,24 @@ import csv
 import sys
 
 
+_POLICIES = {"PolF32": "PolF32", "PolSplitIDF16bLb0": "PolBF16", "PolSplitIDF16_Lb1": "PolF16"}
+
+
+def _unmangle(name: str) -> str:
+    """Readable names for the templated NUDFT kernels that the profiler leaves
+    mangled (their template arguments include 16-bit float types)."""
+    import re
+    m = re.match(r"_ZN3mri12_GLOBAL__N_1\d+(nudft_(?:fwd|adj))INS0_\d+(\w+?)E+Li(\d)E", name)
+    if m:
+        return f"{m.group(1)}<{_POLICIES.get(m.group(2), m.group(2))}, {m.group(3)}>(mri::NudftTable)"
+    m = re.match(r"_ZN3mri12_GLOBAL__N_1\d+(\w+?)ENS_10NudftTableE", name)
+    if m:
+        return f"{m.group(1)}(mri::NudftTable)"
+    return name
+
+
 def short(name: str) -> str:
+    name = _unmangle(name)
     name = name.replace("mri::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
     return name.replace("void ", "")[:90]
 

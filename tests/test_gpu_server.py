@@ -44,7 +44,7 @@ def _submit(srv, wl, p, data):
 MIX = [(24, 24, 3, 6, 48, 11), (40, 32, 5, 10, 80, 12), (16, 20, 2, 5, 32, 13), (64, 64, 9, 12, 128, 14)]
 
 
-@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3])
+@pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3, mri.FP16X3])
 def test_mix_equals_alone_and_oracle(prec):
     reqs = [_req(*m) for m in MIX]
     reqs[1] = _req(40, 32, 5, 10, 80, 12, na=3, ncg=5)      # different counts in the same mix
