@@ -15,8 +15,9 @@ steps.  Also reported:
 * cpu_baseline -- the FP64 NumPy oracle timed on the host on a bounded sample
   (one ADMM iteration with 5 CG steps of the same problem);
 * image_nrmse_vs_oracle -- the timed solve's image against the oracle's own
-  30 x 5 reconstruction of the same data (stored under tests/golden), so the
-  forms (fp32, bf16x3, fp16x3) are compared at their accuracy.
+  30 x 5 reconstruction of the same data (stored under tests/golden), and
+  image_nrmse_vs_phantom against the ground-truth phantom, so the forms
+  (fp32, bf16x3, fp16x3) are compared at their accuracy.
 
 Other workloads (one JSON line each):
 
@@ -144,7 +145,9 @@ def bench_serve(args):
     dev = torch.device("cuda:0")
     g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     payloads, flop = [], 0.0
-    for r in reqs:   # k-space data: F(phantom) on the GPU plus seeded noise, staged on the host
+    for i, r in enumerate(reqs):   # k-space data: F(phantom) on the GPU plus seeded noise, staged on the host
+        if i % 25 == 0:
+            print(f"[serve] preparing request {i}/{len(reqs)}", file=sys.stderr, flush=True)
         p = synth.make_problem(r.wl)
         d = mri.nudft_forward(g(p.truth), g(p.smaps), g(p.traj), precision=mri.FP32)[0].cpu().numpy()
         d = (d + p.noise[0]).astype(np.complex64)
@@ -154,7 +157,7 @@ def bench_serve(args):
     torch.cuda.synchronize()
     arrivals = [r.arrival for r in reqs]
     with serve.Server(int(args.budget_gb * (1 << 30)), max_slots=args.slots, precision=prec) as srv:
-        res = serve.replay(srv, arrivals, payloads)
+        res = serve.replay(srv, arrivals, payloads, progress_s=30.0)
     rec = {
         "metric": "served ADMM-TV reconstructions: p50/p99 latency and recons/s",
         "value": res["recons_per_s"], "unit": "recons/s", "n_gpus": 1, "steps": args.requests, "warmup": 0,
@@ -229,10 +232,12 @@ def main():
         raise RuntimeError(f"solve did not run to completion: {st}")
     iters_per_s = wl.admm_iters * args.steps / (ms_total / 1e3)
     nrmse = None
+    got = out[0].cpu().numpy().astype(np.complex128)
     if golden is not None:
         ref = golden["image"].astype(np.complex128)
-        got = out[0].cpu().numpy().astype(np.complex128)
         nrmse = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    truth0 = p.truth[0].astype(np.complex128)
+    nrmse_truth = float(np.linalg.norm(got - truth0) / np.linalg.norm(truth0))
 
     # Per-kernel timing of the two NUDFT operators at the solve's launch
     # configuration (same kernels, tables and stream as inside admm_solve).
@@ -300,6 +305,7 @@ def main():
                                              "nudft_adjoint": flop / adj_ms / 1e9}},
         "wall_s_timed": wall,
         "image_nrmse_vs_oracle": nrmse,
+        "image_nrmse_vs_phantom": nrmse_truth,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, p)

@@ -152,14 +152,17 @@ class Server:
         return out
 
 
-def replay(server: Server, arrivals: List[float], payloads: List[dict]) -> dict:
+def replay(server: Server, arrivals: List[float], payloads: List[dict], progress_s: float = 0.0) -> dict:
     """Feed requests at their arrival times (seconds from start, wall clock)
     while stepping the server; returns latencies and throughput.
 
-    payloads[i] holds the submit() arguments of request i.
+    payloads[i] holds the submit() arguments of request i.  With progress_s >
+    0 a status line goes to stderr at that interval.
     """
+    import sys
     order = np.argsort(arrivals)
     t0 = time.perf_counter()
+    last_report = t0
     nxt = 0
     running = {}
     lat = np.zeros(len(arrivals))
@@ -181,6 +184,10 @@ def replay(server: Server, arrivals: List[float], payloads: List[dict]) -> dict:
                 i = running.pop(rid)
                 lat[i] = time.perf_counter() - t0 - arrivals[i]
                 finished += 1
+        if progress_s > 0 and time.perf_counter() - last_report >= progress_s:
+            last_report = time.perf_counter()
+            print(f"[replay] t={last_report - t0:.0f}s submitted={nxt} finished={finished}", file=sys.stderr,
+                  flush=True)
     wall = time.perf_counter() - t0 - first_arrival
     return {"latency_s": lat, "wall_s": wall, "recons_per_s": len(arrivals) / wall,
             "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),

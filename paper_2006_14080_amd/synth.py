@@ -167,6 +167,17 @@ ADMM256 = Workload("admm_tv_256x256_c8_r64x512_30x5", 256, 256, 8, 64, 512,
 SLICES384 = Workload("admm_tv_32x384x384_c16_r128x768_40x5", 384, 384, 16, 128, 768,
                      5e-4, 1.0, 40, 5, batch=32, seed=400)
 
+# Paper-shaped stand-ins (Sec. V): a 128 x 64 grid with a 12-channel coil.
+# Fully sampled radial data (101 spokes x 128 samples) for the "inverse DFT"
+# accuracy experiment, and the x8-undersampled set (13 spokes x 128 samples)
+# reconstructed with the Table I parameters (lambda 1e-7, beta 1, relative
+# tolerance 1e-4 over at most 5 ADMM iterations, CG absolute tolerance 1e-6
+# over at most 20 steps).
+INVDFT128x64 = Workload("inverse_dft_128x64_c12_r101x128", 128, 64, 12, 101, 128,
+                        0.0, 1.0, 0, 0, seed=606)
+TABLE1_128x64 = Workload("admm_tv_table1_128x64_c12_r13x128", 128, 64, 12, 13, 128,
+                         1e-7, 1.0, 5, 20, seed=707, rtol=1e-4, atol=1e-6)
+
 
 @dataclasses.dataclass
 class Problem:
