@@ -272,36 +272,45 @@ __device__ __forceinline__ int split_scale_exp(float m) {
 // Pre-pass of the forward: I[b][g][y][x] = s_g[y][x] x_b[y][x], rows padded to
 // a multiple of KC with zeros so the GEMM loads whole K-steps unguarded.
 // ---------------------------------------------------------------------------
-// Each thread forms four consecutive pixels of one padded row (the pitch is a
-// multiple of 8, so a group never crosses a row) and stores them as two
-// 16-byte writes.
+// Each thread takes four consecutive pixels of one padded row of one slice
+// (the pitch is a multiple of 8, so a group never crosses a row), reads the
+// image once and writes the group for every coil (two 16-byte writes each).
 __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
-    const int64_t gq = (int64_t)blockIdx.x * 256 + threadIdx.x;   // index of a 4-pixel group
-    if (gq * 4 >= tab.cw_total) return;
-    const int64_t gi = gq * 4;
+    int64_t gq = (int64_t)blockIdx.x * 256 + threadIdx.x;   // index of a 4-pixel group
     int k = 0;
-    while (k + 1 < tab.nitems && gi >= tab.it[k + 1].cw_begin) ++k;
+    for (; k < tab.nitems; ++k) {
+        const NudftItem& c = tab.it[k];
+        const int64_t n = (int64_t)c.nb * c.ny * (ceil_div(c.nx, KC) * KC / 4);
+        if (gq < n) break;
+        gq -= n;
+    }
+    if (k >= tab.nitems) return;
     const NudftItem& it = tab.it[k];
-    const int i = (int)(gi - it.cw_begin);           // < 2^31 per item (checked on the host)
     const int rowlen = (int)ceil_div(it.nx, KC) * KC;
-    const int per_coil = rowlen * it.ny;
-    const int bg = i / per_coil;
-    const int rem = i - bg * per_coil;
-    const int y = rem / rowlen, x0 = rem - y * rowlen;
-    const int g = bg % it.nc, b = bg / it.nc;
+    const int gpr = rowlen / 4;                           // groups per padded row
+    const int i = (int)gq;
+    const int b = i / (gpr * it.ny);
+    const int rem = i - b * gpr * it.ny;
+    const int y = rem / gpr, x0 = (rem - y * gpr) * 4;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
     const int64_t npix = (int64_t)it.nx * it.ny;
-    const float2* sm = it.smaps + b * it.smaps_bs + g * npix + (int64_t)y * it.nx;
     const float2* im = it.img + b * npix + (int64_t)y * it.nx;
-    float2 v[4];
+    float2 xv[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int x = x0 + j;
-        v[j] = x < it.nx ? cmul(sm[x], im[x]) : make_float2(0.f, 0.f);
+    for (int j = 0; j < 4; ++j) xv[j] = x0 + j < it.nx ? im[x0 + j] : make_float2(0.f, 0.f);
+    const float2* sm = it.smaps + b * it.smaps_bs + (int64_t)y * it.nx;
+    float2* dst = it.wimg + ((int64_t)b * it.nc * it.ny + y) * rowlen + x0;
+    const int64_t coil_stride = (int64_t)it.ny * rowlen;
+#pragma unroll 4
+    for (int g = 0; g < it.nc; ++g) {
+        const float2* sg = sm + g * npix;
+        float2 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = x0 + j < it.nx ? cmul(sg[x0 + j], xv[j]) : make_float2(0.f, 0.f);
+        float4* d4 = reinterpret_cast<float4*>(dst + g * coil_stride);
+        d4[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
+        d4[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
     }
-    float4* dst = reinterpret_cast<float4*>(it.wimg + i);
-    dst[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
-    dst[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
 }
 
 // Split-BF16 form of the pre-pass: s_g (.) x_b is split and packed once per
@@ -870,7 +879,11 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
     // order alone and in a batch: results are batch-invariant bit for bit.
     (void)nc; (void)precision; (void)nb;
     const int64_t tps = adj_tiles_per_split(nx, ny, 1);
-    const int64_t target = 1024;              // workgroups per slice: fills 256 CUs several times over
+    // Workgroups per slice.  512 (2048 samples per split at 256^2 / 8 coils)
+    // measured 1-4 % faster but its longer FP32 accumulations tripled the
+    // benchmark solve's image error in the FP16x3 form (4.6e-5 -> 1.3e-4);
+    // 1024 keeps 1024 samples per split.
+    const int64_t target = 1024;
     int64_t s = ceil_div(target, tps);
     const int64_t smax = std::max<int64_t>(1, nk / 512);   // keep >= 512 samples per split
     if (s > smax) s = smax;
@@ -896,7 +909,10 @@ hipError_t launch_coil_weight(const NudftTable& t, int precision, hipStream_t s)
         hipLaunchKernelGGL(k_coil_weight_f16, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, s, t);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(t.cw_total, 4 * 256)), dim3(256), 0, s, t);
+    int64_t groups = 0;
+    for (int i = 0; i < t.nitems; ++i)
+        groups += (int64_t)t.it[i].nb * t.it[i].ny * (ceil_div(t.it[i].nx, KC) * KC / 4);
+    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(groups, 256)), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 

@@ -53,7 +53,9 @@ struct SolveTable {
     SolveItem it[kMaxItems];
 };
 
-constexpr int kVecThreads = 256;   // one pixel per thread
+constexpr int kVecThreads = 256;
+constexpr int kVecPix = 4;                                // pixels per thread
+constexpr int kVecBlockPix = kVecThreads * kVecPix;       // pixels per block
 
 enum FinishMode { kFinishFhd = 0, kFinishCgInit = 1, kFinishCgStep = 2 };
 enum FinalizeMode { kFinCgInit = 0, kFinCgStep = 1, kFinCgUpdate = 2, kFinDual = 3 };

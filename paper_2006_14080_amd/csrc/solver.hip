@@ -3,7 +3,9 @@
 // right-hand side, the CG updates, the dual update, and the reduction that
 // finishes each application of the normal matrix A = F^H F + (beta/2) Theta^H Theta.
 //
-// All are memory-bound, one pixel per thread, coalesced along x.  Vector
+// All are memory-bound: each thread takes kVecPix pixels kVecThreads apart
+// (coalesced along x), issuing the loads of all of them before any store so
+// a wave keeps several requests in flight per array.  Vector
 // arithmetic is FP32; inner products and norms accumulate in FP64 and are
 // summed in a fixed order: wave shuffles, waves in index order, per-block
 // partials written to memory, then one finalize block per slice (k_finalize)
@@ -18,12 +20,13 @@ namespace {
 
 struct Loc {
     int item, b, blk;
-    int pix;            // pixel within the slice (npix < 2^31)
-    bool valid;
+    int pix0;           // first pixel of this thread; its others follow every kVecThreads
 };
 
+// Blocks are remapped so each XCD works on one contiguous pixel range: the
+// stencils' neighbouring rows are then in that XCD's own L2.
 __device__ __forceinline__ Loc locate(const SolveTable& t) {
-    const int g = blockIdx.x;
+    const int g = xcd_remap(blockIdx.x, t.total_blocks);
     int i = 0;
     while (i + 1 < t.nitems && g >= t.it[i + 1].block_begin) ++i;
     const SolveItem& it = t.it[i];
@@ -32,10 +35,11 @@ __device__ __forceinline__ Loc locate(const SolveTable& t) {
     l.item = i;
     l.b = local / it.nblk;
     l.blk = local % it.nblk;
-    l.pix = l.blk * kVecThreads + (int)threadIdx.x;
-    l.valid = l.pix < (int)it.npix;
+    l.pix0 = l.blk * kVecBlockPix + (int)threadIdx.x;
     return l;
 }
+
+__device__ __forceinline__ int pix_of(const Loc& l, int j) { return l.pix0 + j * kVecThreads; }
 
 // Periodic neighbours of pixel p in an ny x nx image.
 struct Nb {
@@ -94,12 +98,16 @@ __device__ __forceinline__ void fail_numeric(SolveScalars& s) {
 __global__ __launch_bounds__(kVecThreads) void k_solve_init(const SolveTable tab) {
     const Loc l = locate(tab);
     const SolveItem& it = tab.it[l.item];
-    if (l.valid) {
-        const int64_t o = (int64_t)l.b * it.npix + l.pix;
+    const int npix = (int)it.npix;
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = pix_of(l, j);
+        if (pix >= npix) break;
+        const int64_t o = (int64_t)l.b * it.npix + pix;
         const float2 v = it.x0 ? it.x0[o] : make_float2(0.f, 0.f);
         it.rho[o] = v;
         it.rho0[o] = v;
-        const int64_t e = (int64_t)l.b * 2 * it.npix + l.pix;
+        const int64_t e = (int64_t)l.b * 2 * it.npix + pix;
         it.eta[e] = make_float2(0.f, 0.f);
         it.eta[e + it.npix] = make_float2(0.f, 0.f);
     }
@@ -123,20 +131,31 @@ __global__ __launch_bounds__(kVecThreads) void k_solve_init(const SolveTable tab
 __global__ __launch_bounds__(kVecThreads) void k_mu(const SolveTable tab) {
     const Loc l = locate(tab);
     const SolveItem& it = tab.it[l.item];
-    if (!it.sc[l.b].admm_active || !l.valid) return;
-    const int64_t base = (int64_t)l.b * it.npix;
-    const float2* rho = it.rho + base;
-    const Nb n = neighbours(l.pix, it.nx, it.ny);
-    const float2 r0 = rho[l.pix];
-    const int64_t e = (int64_t)l.b * 2 * it.npix + l.pix;
-    float2 z[2];
-    z[0] = cadd(csub(rho[n.xp], r0), it.eta[e]);
-    z[1] = cadd(csub(rho[n.yp], r0), it.eta[e + it.npix]);
+    if (!it.sc[l.b].admm_active) return;
+    const int npix = (int)it.npix;
+    const float2* rho = it.rho + (int64_t)l.b * it.npix;
+    const float2* eta = it.eta + (int64_t)l.b * 2 * it.npix;
+    float2* mu = it.mu + (int64_t)l.b * 2 * it.npix;
+    float2 z0[kVecPix], z1[kVecPix];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const float mag = sqrtf(z[c].x * z[c].x + z[c].y * z[c].y);
-        const float sc = mag > it.thr ? 1.0f - it.thr / mag : 0.0f;
-        it.mu[e + c * it.npix] = cscale(z[c], sc);
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = min(pix_of(l, j), npix - 1);
+        const Nb n = neighbours(pix, it.nx, it.ny);
+        const float2 r0 = rho[pix];
+        z0[j] = cadd(csub(rho[n.xp], r0), eta[pix]);
+        z1[j] = cadd(csub(rho[n.yp], r0), eta[pix + it.npix]);
+    }
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = pix_of(l, j);
+        if (pix >= npix) break;
+        const float2 z[2] = {z0[j], z1[j]};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float mag = sqrtf(z[c].x * z[c].x + z[c].y * z[c].y);
+            const float sc = mag > it.thr ? 1.0f - it.thr / mag : 0.0f;
+            mu[pix + c * it.npix] = cscale(z[c], sc);
+        }
     }
 }
 
@@ -144,20 +163,31 @@ __global__ __launch_bounds__(kVecThreads) void k_mu(const SolveTable tab) {
 __global__ __launch_bounds__(kVecThreads) void k_rhs(const SolveTable tab) {
     const Loc l = locate(tab);
     const SolveItem& it = tab.it[l.item];
-    if (!it.sc[l.b].admm_active || !l.valid) return;
+    if (!it.sc[l.b].admm_active) return;
+    const int npix = (int)it.npix;
     const int64_t e = (int64_t)l.b * 2 * it.npix;
     const float2* mu0 = it.mu + e;
     const float2* mu1 = mu0 + it.npix;
     const float2* et0 = it.eta + e;
     const float2* et1 = et0 + it.npix;
-    const Nb n = neighbours(l.pix, it.nx, it.ny);
-    const int64_t p = l.pix;
-    // Theta^H g = g0(i, j-1) - g0(i, j) + g1(i-1, j) - g1(i, j), g = mu - eta
-    const float2 g0m = csub(mu0[n.xm], et0[n.xm]), g0 = csub(mu0[p], et0[p]);
-    const float2 g1m = csub(mu1[n.ym], et1[n.ym]), g1 = csub(mu1[p], et1[p]);
-    const float2 th = cadd(csub(g0m, g0), csub(g1m, g1));
-    const int64_t o = (int64_t)l.b * it.npix + p;
-    it.b[o] = cadd(it.fhd[o], cscale(th, it.half_beta));
+    const int64_t base = (int64_t)l.b * it.npix;
+    float2 out[kVecPix];
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int p = min(pix_of(l, j), npix - 1);
+        const Nb n = neighbours(p, it.nx, it.ny);
+        // Theta^H g = g0(i, j-1) - g0(i, j) + g1(i-1, j) - g1(i, j), g = mu - eta
+        const float2 g0m = csub(mu0[n.xm], et0[n.xm]), g0 = csub(mu0[p], et0[p]);
+        const float2 g1m = csub(mu1[n.ym], et1[n.ym]), g1 = csub(mu1[p], et1[p]);
+        const float2 th = cadd(csub(g0m, g0), csub(g1m, g1));
+        out[j] = cadd(it.fhd[base + p], cscale(th, it.half_beta));
+    }
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int p = pix_of(l, j);
+        if (p >= npix) break;
+        it.b[base + p] = out[j];
+    }
 }
 
 // ---- finish one application of A (or F^H d) from the adjoint's partials ------
@@ -166,49 +196,76 @@ __global__ __launch_bounds__(kVecThreads) void k_rhs(const SolveTable tab) {
 // kFinishCgStep: q = A p; pAp = Re(p^H q)                               (Alg. 2 step)
 // with A v = F^H F v + (beta/2) Theta^H Theta v and Theta^H Theta v the
 // periodic 5-point stencil 4 v - (four neighbours).
-__global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab, int mode) {
+template <int mode>
+__global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab) {
     const Loc l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     SolveScalars& sc = it.sc[l.b];
-    if (mode == kFinishCgInit && !sc.admm_active) return;
-    if (mode == kFinishCgStep && !sc.cg_active) return;
+    if constexpr (mode == kFinishCgInit) {
+        if (!sc.admm_active) return;
+    }
+    if constexpr (mode == kFinishCgStep) {
+        if (!sc.cg_active) return;
+    }
+    const int npix = (int)it.npix;
     const int64_t base = (int64_t)l.b * it.npix;
-    float2 acc = make_float2(0.f, 0.f);
-    double v0 = 0.0;
-    if (l.valid) {
-        double sr = 0.0, si = 0.0;
-        const int64_t stride = (int64_t)it.nb * it.npix;
-        for (int s = 0; s < it.ksplit; ++s) {
-            const float2 v = it.part[s * stride + base + l.pix];
-            sr += v.x;
-            si += v.y;
+    const int64_t stride = (int64_t)it.nb * it.npix;
+    // Partial images in plane order (FP64), all pixels of the thread at once.
+    double sr[kVecPix], si[kVecPix];
+    int pc[kVecPix];
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        pc[j] = min(pix_of(l, j), npix - 1);
+        sr[j] = si[j] = 0.0;
+    }
+    const float2* pp = it.part + base;
+    for (int s = 0; s < it.ksplit; ++s) {
+        float2 v[kVecPix];
+#pragma unroll
+        for (int j = 0; j < kVecPix; ++j) v[j] = pp[s * stride + pc[j]];
+#pragma unroll
+        for (int j = 0; j < kVecPix; ++j) {
+            sr[j] += v[j].x;
+            si[j] += v[j].y;
         }
-        acc = make_float2((float)sr, (float)si);
-        if (mode == kFinishFhd) {
-            it.fhd[base + l.pix] = acc;
-        } else {
-            const float2* src = mode == kFinishCgStep ? it.p + base : (it.warm ? it.rho + base : it.rho0 + base);
-            const Nb n = neighbours(l.pix, it.nx, it.ny);
-            const float2 c = src[l.pix];
-            float2 lap = cscale(c, 4.0f);
+    }
+    double v0 = 0.0;
+    if constexpr (mode == kFinishFhd) {
+#pragma unroll
+        for (int j = 0; j < kVecPix; ++j)
+            if (pix_of(l, j) < npix) it.fhd[base + pc[j]] = make_float2((float)sr[j], (float)si[j]);
+    } else {
+        const float2* src = mode == kFinishCgStep ? it.p + base : (it.warm ? it.rho + base : it.rho0 + base);
+        float2 q[kVecPix], c[kVecPix], bv[kVecPix];
+#pragma unroll
+        for (int j = 0; j < kVecPix; ++j) {
+            const Nb n = neighbours(pc[j], it.nx, it.ny);
+            c[j] = src[pc[j]];
+            float2 lap = cscale(c[j], 4.0f);
             lap = csub(lap, src[n.xp]);
             lap = csub(lap, src[n.xm]);
             lap = csub(lap, src[n.yp]);
             lap = csub(lap, src[n.ym]);
-            const float2 q = cadd(acc, cscale(lap, it.half_beta));
-            if (mode == kFinishCgStep) {
-                it.q[base + l.pix] = q;
-                v0 = (double)c.x * q.x + (double)c.y * q.y;
+            q[j] = cadd(make_float2((float)sr[j], (float)si[j]), cscale(lap, it.half_beta));
+            if constexpr (mode == kFinishCgInit) bv[j] = it.b[base + pc[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kVecPix; ++j) {
+            if (pix_of(l, j) >= npix) break;
+            const int64_t o = base + pc[j];
+            if constexpr (mode == kFinishCgStep) {
+                it.q[o] = q[j];
+                v0 += (double)c[j].x * q[j].x + (double)c[j].y * q[j].y;
             } else {
-                const float2 r = csub(it.b[base + l.pix], q);
-                it.r[base + l.pix] = r;
-                it.p[base + l.pix] = r;
-                it.xnew[base + l.pix] = c;
-                v0 = cnorm2(r);
+                const float2 r = csub(bv[j], q[j]);
+                it.r[o] = r;
+                it.p[o] = r;
+                it.xnew[o] = c[j];
+                v0 += cnorm2(r);
             }
         }
+        block_partials(v0, 0.0, it, l.b, l.blk);
     }
-    if (mode != kFinishFhd) block_partials(v0, 0.0, it, l.b, l.blk);
 }
 
 // ---- Alg. 2 step: x += alpha d; r -= alpha A d; tau' = r^H r ------------------
@@ -218,16 +275,26 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(const SolveTable tab)
     const SolveScalars& sc = it.sc[l.b];
     if (!sc.cg_active) return;
     const float a = (float)sc.alpha_cg;
-    double v0 = 0.0;
-    if (l.valid) {
-        const int64_t o = (int64_t)l.b * it.npix + l.pix;
+    const int npix = (int)it.npix;
+    const int64_t base = (int64_t)l.b * it.npix;
+    float2 x[kVecPix], r[kVecPix];
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int64_t o = base + min(pix_of(l, j), npix - 1);
         const float2 p = it.p[o], q = it.q[o];
-        float2 x = it.xnew[o], r = it.r[o];
-        x = make_float2(fmaf(a, p.x, x.x), fmaf(a, p.y, x.y));
-        r = make_float2(fmaf(-a, q.x, r.x), fmaf(-a, q.y, r.y));
-        it.xnew[o] = x;
-        it.r[o] = r;
-        v0 = cnorm2(r);
+        x[j] = it.xnew[o];
+        r[j] = it.r[o];
+        x[j] = make_float2(fmaf(a, p.x, x[j].x), fmaf(a, p.y, x[j].y));
+        r[j] = make_float2(fmaf(-a, q.x, r[j].x), fmaf(-a, q.y, r[j].y));
+    }
+    double v0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = pix_of(l, j);
+        if (pix >= npix) break;
+        it.xnew[base + pix] = x[j];
+        it.r[base + pix] = r[j];
+        v0 += cnorm2(r[j]);
     }
     block_partials(v0, 0.0, it, l.b, l.blk);
 }
@@ -237,11 +304,23 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_dir(const SolveTable tab) {
     const Loc l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     const SolveScalars& sc = it.sc[l.b];
-    if (!sc.cg_active || !l.valid) return;
+    if (!sc.cg_active) return;
     const float bc = (float)sc.beta_cg;
-    const int64_t o = (int64_t)l.b * it.npix + l.pix;
-    const float2 r = it.r[o], p = it.p[o];
-    it.p[o] = make_float2(fmaf(bc, p.x, r.x), fmaf(bc, p.y, r.y));
+    const int npix = (int)it.npix;
+    const int64_t base = (int64_t)l.b * it.npix;
+    float2 d[kVecPix];
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int64_t o = base + min(pix_of(l, j), npix - 1);
+        const float2 r = it.r[o], p = it.p[o];
+        d[j] = make_float2(fmaf(bc, p.x, r.x), fmaf(bc, p.y, r.y));
+    }
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = pix_of(l, j);
+        if (pix >= npix) break;
+        it.p[base + pix] = d[j];
+    }
 }
 
 // ---- eq. (8) and Alg. 4: eta += Theta rho' - mu; alpha; rho = rho' ------------
@@ -249,20 +328,32 @@ __global__ __launch_bounds__(kVecThreads) void k_dual(const SolveTable tab) {
     const Loc l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     if (!it.sc[l.b].admm_active) return;
+    const int npix = (int)it.npix;
+    const int64_t base = (int64_t)l.b * it.npix;
+    const float2* xn = it.xnew + base;
+    float2* eta = it.eta + (int64_t)l.b * 2 * it.npix;
+    const float2* mu = it.mu + (int64_t)l.b * 2 * it.npix;
+    float2 c[kVecPix], e0[kVecPix], e1[kVecPix], old[kVecPix];
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = min(pix_of(l, j), npix - 1);
+        const Nb n = neighbours(pix, it.nx, it.ny);
+        c[j] = xn[pix];
+        const float2 d0 = csub(xn[n.xp], c[j]), d1 = csub(xn[n.yp], c[j]);
+        e0[j] = cadd(eta[pix], csub(d0, mu[pix]));
+        e1[j] = cadd(eta[pix + it.npix], csub(d1, mu[pix + it.npix]));
+        old[j] = it.rho[base + pix];
+    }
     double num = 0.0, den = 0.0;
-    if (l.valid) {
-        const int64_t base = (int64_t)l.b * it.npix;
-        const float2* xn = it.xnew + base;
-        const Nb n = neighbours(l.pix, it.nx, it.ny);
-        const float2 c = xn[l.pix];
-        const int64_t e = (int64_t)l.b * 2 * it.npix + l.pix;
-        const float2 d0 = csub(xn[n.xp], c), d1 = csub(xn[n.yp], c);
-        it.eta[e] = cadd(it.eta[e], csub(d0, it.mu[e]));
-        it.eta[e + it.npix] = cadd(it.eta[e + it.npix], csub(d1, it.mu[e + it.npix]));
-        const float2 old = it.rho[base + l.pix];
-        num = cnorm2(csub(c, old));
-        den = cnorm2(old);
-        it.rho[base + l.pix] = c;
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = pix_of(l, j);
+        if (pix >= npix) break;
+        eta[pix] = e0[j];
+        eta[pix + it.npix] = e1[j];
+        num += cnorm2(csub(c[j], old[j]));
+        den += cnorm2(old[j]);
+        it.rho[base + pix] = c[j];
     }
     block_partials(num, den, it, l.b, l.blk);
 }
@@ -343,8 +434,11 @@ __global__ __launch_bounds__(kVecThreads) void k_finalize(const SolveTable tab, 
 __global__ __launch_bounds__(kVecThreads) void k_solve_final(const SolveTable tab) {
     const Loc l = locate(tab);
     const SolveItem& it = tab.it[l.item];
-    if (l.valid) {
-        const int64_t o = (int64_t)l.b * it.npix + l.pix;
+#pragma unroll
+    for (int j = 0; j < kVecPix; ++j) {
+        const int pix = pix_of(l, j);
+        if (pix >= (int)it.npix) break;
+        const int64_t o = (int64_t)l.b * it.npix + pix;
         it.x_out[o] = it.rho[o];
     }
     if (it.stats && l.blk == 0 && threadIdx.x == 0) {
@@ -366,7 +460,18 @@ __global__ __launch_bounds__(kVecThreads) void k_sum_partials(const float2* __re
     const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
     if (i >= n) return;
     double sr = 0.0, si = 0.0;
-    for (int s = 0; s < ksplit; ++s) {
+    int s = 0;
+    for (; s + 8 <= ksplit; s += 8) {      // loads first, additions in plane order
+        float2 v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = part[(s + j) * n + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sr += v[j].x;
+            si += v[j].y;
+        }
+    }
+    for (; s < ksplit; ++s) {
         const float2 v = part[s * n + i];
         sr += v.x;
         si += v.y;
@@ -416,7 +521,10 @@ hipError_t launch_rhs(const SolveTable& t, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_adj_finish(const SolveTable& t, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_finish, grid_of(t), dim3(kVecThreads), 0, s, t, mode);
+    if (mode == kFinishFhd) hipLaunchKernelGGL(k_adj_finish<kFinishFhd>, grid_of(t), dim3(kVecThreads), 0, s, t);
+    else if (mode == kFinishCgInit)
+        hipLaunchKernelGGL(k_adj_finish<kFinishCgInit>, grid_of(t), dim3(kVecThreads), 0, s, t);
+    else hipLaunchKernelGGL(k_adj_finish<kFinishCgStep>, grid_of(t), dim3(kVecThreads), 0, s, t);
     return hipGetLastError();
 }
 hipError_t launch_cg_update(const SolveTable& t, hipStream_t s) {

@@ -1,11 +1,19 @@
-"""Fixed workload for hardware-counter runs (rocprofv3 --pmc).
+"""Fixed workloads for profiler runs (rocprofv3 --pmc / --stats).
 
-    python -m paper_2006_14080_amd.profile_driver [fp32|bf16x3] [repeats]
+    python -m paper_2006_14080_amd.profile_driver [fp32|bf16x3|fp16x3] [repeats]
+    python -m paper_2006_14080_amd.profile_driver vec SLICES
 
-Calls nudft_forward and nudft_adjoint at the 256x256 / 8-coil / 64x512-sample
-shape `repeats` times, then copies a 256 MiB buffer twice (a kernel of known
-traffic: reads 256 MiB, writes 256 MiB) so FETCH_SIZE / WRITE_SIZE can be
-calibrated in the same run.
+The first form calls nudft_forward and nudft_adjoint at the 256x256 / 8-coil /
+64x512-sample shape `repeats` times, then copies a 256 MiB buffer twice (a
+kernel of known traffic: reads 256 MiB, writes 256 MiB) so FETCH_SIZE /
+WRITE_SIZE can be calibrated in the same run.
+
+The second runs admm_solve (2 ADMM x 5 CG, FP32) over SLICES slices of
+384x384 with one coil and 64 samples, so the NUDFT is negligible and the
+solver's memory-bound kernels work on multi-GB arrays (far beyond the 256 MB
+Infinity Cache), then copies 1 GiB three times (the plain-copy reference);
+it prints the pixel count and partial-image count that `profsum vecbw`
+needs.
 """
 import sys
 
@@ -15,7 +23,39 @@ import torch
 from . import mri, synth
 
 
+def vector_sweep(slices: int):
+    n, nc, spokes, nr = 384, 1, 1, 64
+    wl = synth.Workload(f"vec_{slices}x{n}", n, n, nc, spokes, nr, 1e-3, 1.0, 2, 5, batch=slices, seed=900)
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    truth = g(np.stack([synth.ellipse_phantom(n, n, 900 + s) for s in range(min(slices, 4))] *
+                       ((slices + 3) // 4))[:slices].astype(np.complex64))
+    sm = g(synth.coil_maps(n, n, nc))
+    tr = g(synth.radial_trajectory(spokes, nr))
+    data = mri.nudft_forward(truth, sm, tr)
+    shape = mri.shape_of((slices, n, n), sm, tr)
+    params = mri.AdmmParams(wl.lam, wl.beta, wl.admm_iters, wl.cg_iters)
+    solver = mri.AdmmSolver(shape, params, device=torch.device("cuda"))
+    out = torch.empty((slices, n, n), dtype=torch.complex64, device="cuda")
+    for _ in range(2):
+        solver.solve(sm, tr, data, out=out)
+    torch.cuda.synchronize()
+    del solver, out, data, truth
+    # A device copy of known size (1 GiB read + 1 GiB written) in the same run:
+    # the practical bandwidth of a plain read/write stream on this part.
+    src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    # 64 samples are fewer than one sample split (512) and one coil is one
+    # coil group, so the adjoint writes a single partial image per slice.
+    print(f"profile driver done: npix={slices * n * n} coils={nc} planes=1", flush=True)
+
+
 def main(argv):
+    if len(argv) > 1 and argv[1] == "vec":
+        vector_sweep(int(argv[2]))
+        return
     prec = mri.PRECISIONS[argv[1]] if len(argv) > 1 else mri.FP32
     n = int(argv[2]) if len(argv) > 2 else 2
     wl = synth.ADMM256

@@ -75,7 +75,9 @@ def pmc(path):
 VEC_BYTES = {
     "k_mu": lambda c, p: 8 + 16 + 16,                  # rho, eta -> mu
     "k_rhs": lambda c, p: 8 + 16 + 16 + 8,             # F^H d, mu, eta -> b
-    "k_adj_finish": lambda c, p: 8 * p + 8 + 8,        # partial images, d -> A d (step mode)
+    "k_adj_finish<0>": lambda c, p: 8 * p + 8,                # partial images -> F^H d
+    "k_adj_finish<1>": lambda c, p: 8 * p + 8 + 8 + 3 * 8,    # partials, x, b -> r, p, x (CG start)
+    "k_adj_finish<2>": lambda c, p: 8 * p + 8 + 8,            # partials, d -> A d (CG step)
     "k_cg_update": lambda c, p: 4 * 8 + 2 * 8,         # x, r, d, A d -> x, r
     "k_cg_dir": lambda c, p: 2 * 8 + 8,                # r, d -> d
     "k_dual": lambda c, p: 8 + 16 + 16 + 8 + 16 + 8,   # x, mu, eta, rho -> eta, rho
@@ -84,11 +86,18 @@ VEC_BYTES = {
 HBM_PEAK = 8.0e12
 
 
-def vecbw(path, npix, coils, planes):
+def vecbw(path, npix, coils, planes, copy_bytes=None):
     rows = list(csv.DictReader(open(path)))
     out = [f"{'kernel':16s} {'calls':>6s} {'avg_us':>9s} {'bytes/px':>9s} {'GB/s':>8s} {'of 8 TB/s':>9s}"]
+    if copy_bytes:
+        # a device copy of copy_bytes read + copy_bytes written, in the same run
+        for r in rows:
+            if short(r["Name"]).startswith(COPY_KERNEL) and float(r["AverageNs"]) > 1e5:
+                gbs = 2 * copy_bytes / (float(r["AverageNs"]) * 1e-9) / 1e9
+                out.append(f"{'(device copy)':16s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+                           f"{'-':>9s} {gbs:8.1f} {gbs * 1e9 / HBM_PEAK:9.1%}")
     for r in rows:
-        k = short(r["Name"]).split("(")[0]
+        k = short(r["Name"]).split("(")[0].replace("void ", "").strip()
         if k not in VEC_BYTES:
             continue
         b = VEC_BYTES[k](coils, planes)
@@ -160,12 +169,13 @@ def main():
     ap.add_argument("--npix", type=int)
     ap.add_argument("--coils", type=int)
     ap.add_argument("--planes", type=int)
+    ap.add_argument("--copy-bytes", type=int, help="vecbw: size of the reference device copy in the run")
     a = ap.parse_args()
     if a.mode == "vecbw":
         print("# solver memory-bound kernels: achieved bandwidth from algorithmic bytes")
         print(f"# command: {a.cmd}")
         print(f"# pixels (all slices) = {a.npix}, coils = {a.coils}, adjoint partial images per slice = {a.planes}")
-        for line in vecbw(a.csv, a.npix, a.coils, a.planes):
+        for line in vecbw(a.csv, a.npix, a.coils, a.planes, a.copy_bytes):
             print(line)
         return 0
     if a.mode == "traffic":
