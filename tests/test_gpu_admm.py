@@ -42,9 +42,17 @@ def _oracle(p, data, b, lam, beta, na, nc, **kw):
     return oadmm.admm(data[b], p.smaps, p.traj, lam, beta, na, nc, **kw)
 
 
+# BF16x3 keeps ~16 bits per operand (per-operator error 3.8e-6); the solves
+# amplify operator errors 10-1000x (FP32's 2-6e-7 become 2-7e-5 at 30x5), so
+# its image lands between 2e-5 and 5e-3 depending on rounding details.  It is
+# held to 1e-3 on the 32x32 case and reported (within (1e-4, 1e-2]) at full
+# size; FP32 and FP16x3 meet the 1e-4 bar everywhere.
+BAR = {mri.FP32: NRMSE, mri.FP16X3: NRMSE, mri.BF16X3: 1e-3}
+
+
 @pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3, mri.FP16X3])
 def test_admm32_full_counts(prec):
-    # FP32: the plain 32x32 workload; BF16X3: its split-BF16 precision form.
+    # The plain 32x32 workload (10 ADMM x 3 CG) in each precision form.
     wl = synth.ADMM32
     p = synth.make_problem(wl)
     data = _data(p)
@@ -52,7 +60,9 @@ def test_admm32_full_counts(prec):
     ref = _oracle(p, data, 0, wl.lam, wl.beta, wl.admm_iters, wl.cg_iters)
     assert st[0]["status"] == 0
     assert st[0]["admm_iters"] == ref.admm_iters and st[0]["cg_steps"] == ref.cg_steps
-    assert nrmse(img[0], ref.image) <= NRMSE
+    e = nrmse(img[0], ref.image)
+    print(f"{mri.PRECISION_NAMES[prec]}: 32x32 10x3 image NRMSE vs oracle {e:.3e}")
+    assert e <= BAR[prec]
 
 
 @pytest.mark.parametrize("warm", [True, False])
@@ -145,8 +155,8 @@ def test_admm256_full_counts_against_stored_oracle(prec):
 
 def test_admm256_full_counts_bf16x3_reported_error():
     # The bf16 split keeps ~16 bits per operand (per-operator error ~4e-6);
-    # 150 CG steps carry that to an image NRMSE of about 3e-3 on this problem,
-    # above the 1e-4 bar that FP32 and FP16x3 meet.  Held here to its
-    # measured size so a regression shows.
+    # 150 CG steps carry that to an image NRMSE of 5e-4 .. 3e-3 on this
+    # problem (by build), above the 1e-4 bar that FP32 and FP16x3 meet.  Held
+    # here to its measured range so a regression shows.
     e = _admm256_full(mri.BF16X3)
     assert 1e-4 < e <= 1e-2
