@@ -67,6 +67,14 @@ def pmc(path):
         avg_us = sum(dur[k].values()) / max(1, len(dur[k]))
         items = ", ".join(f"{c}={v / n:.6g}" for c, v in sorted(counters.items()))
         out.append(f"{k}: dispatches={n} avg_us={avg_us:.2f} {items}")
+        # Derived: matrix-core busy fraction (four SIMDs per CU) and VALU
+        # instructions per MFMA instruction.
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in counters and counters.get("SQ_BUSY_CU_CYCLES"):
+            busy = counters["SQ_VALU_MFMA_BUSY_CYCLES"] / (4.0 * counters["SQ_BUSY_CU_CYCLES"])
+            extra = f"  -> matrix cores busy {busy:.1%} of CU-busy cycles"
+            if counters.get("SQ_INSTS_MFMA"):
+                extra += f", {counters.get('SQ_INSTS_VALU', 0.0) / counters['SQ_INSTS_MFMA']:.1f} VALU per MFMA"
+            out.append(extra)
     return out
 
 
