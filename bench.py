@@ -180,8 +180,8 @@ def bench_serve(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
-              "k-space split is design-only in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
+              "multi-GPU k-space split (its design is documented, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "slices384":
         return bench_slices(args)

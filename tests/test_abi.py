@@ -23,7 +23,7 @@ def _declared_functions():
 @pytest.fixture(scope="module")
 def lib():
     if not os.path.exists(mri.LIB_PATH):
-        pytest.fail("libmriadmm.so has not been built (run __graft_entry__.build())")
+        pytest.fail("libmriadmm.so has not been built (run python -m paper_2006_14080_amd.build)")
     return mri.load()
 
 
