@@ -151,6 +151,19 @@ def test_full_size_sampled(wl, batch, prec):
         assert rel(a[b][rows, cols], ref) <= TOL
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("nx,ny,nc,nk", [(2048, 3, 64, 700), (5, 2048, 7, 333)])
+def test_maximum_dimensions(nx, ny, nc, nk, prec):
+    # MRI_MAX_DIM rows or columns with MRI_MAX_COILS coils: 256 K-steps per
+    # forward pass along x, or eight 256-row passes along y; 8 coil groups in
+    # the adjoint.
+    img, sm, tr, dat = _inputs(nx, ny, nc, nk, 1, 85)
+    f = mri.nudft_forward(_gpu(img), _gpu(sm), _gpu(tr), precision=prec).cpu().numpy()[0]
+    a = mri.nudft_adjoint(_gpu(dat), _gpu(sm), _gpu(tr), ny, nx, precision=prec).cpu().numpy()[0]
+    assert rel(f, onudft.forward(img[0], sm, tr)) <= TOL
+    assert rel(a, onudft.adjoint(dat[0], sm, tr)) <= TOL
+
+
 def test_split_forms_error_ordering():
     # Per-operator error of each form on one mid-size problem.  The bf16 split
     # keeps ~16 bits per operand and its product error dominates; the fp16

@@ -124,3 +124,18 @@ def test_nonfinite_request_is_isolated():
     assert out[ib][1]["status"] == -5
     assert out[ig][1]["status"] == 0
     assert np.array_equal(out[ig][0], _alone(*good, mri.FP32)[0])
+
+
+def test_all_slots_busy_grouped_launches():
+    # MRI_SERVER_MAX_SLOTS requests of 16 different shapes in flight at once:
+    # every grouped launch carries the maximum of 16 problems; each result
+    # still equals its solve alone, bit for bit.
+    reqs = [_req(12 + 2 * i, 10 + (3 * i) % 11, 1 + i % 5, 3 + i % 4, 24 + 4 * i, 60 + i, na=2 + i % 3, ncg=2)
+            for i in range(16)]
+    with serve.Server(1 << 30, max_slots=16) as srv:
+        ids = [_submit(srv, *r) for r in reqs]
+        srv.step()
+        assert srv.info()["active"] == 16
+        out = srv.run_until_idle(ids)
+    for rid, (wl, p, data) in zip(ids, reqs):
+        assert np.array_equal(out[rid][0], _alone(wl, p, data, mri.FP32)[0]), wl.name
