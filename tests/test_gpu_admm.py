@@ -45,8 +45,8 @@ def _oracle(p, data, b, lam, beta, na, nc, **kw):
 # BF16x3 keeps ~16 bits per operand (per-operator error 3.8e-6); the solves
 # amplify operator errors 10-1000x (FP32's 2-6e-7 become 2-7e-5 at 30x5), so
 # its image lands between 2e-5 and 5e-3 depending on rounding details.  It is
-# held to 1e-3 on the 32x32 case and reported (within (1e-4, 1e-2]) at full
-# size; FP32 and FP16x3 meet the 1e-4 bar everywhere.
+# held to 1e-3 on the 32x32 case and to 1e-2 at full size; FP32 and FP16x3
+# meet the 1e-4 bar everywhere.
 BAR = {mri.FP32: NRMSE, mri.FP16X3: NRMSE, mri.BF16X3: 1e-3}
 
 
@@ -155,8 +155,9 @@ def test_admm256_full_counts_against_stored_oracle(prec):
 
 def test_admm256_full_counts_bf16x3_reported_error():
     # The bf16 split keeps ~16 bits per operand (per-operator error ~4e-6);
-    # 150 CG steps carry that to an image NRMSE of 5e-4 .. 3e-3 on this
-    # problem (by build), above the 1e-4 bar that FP32 and FP16x3 meet.  Held
-    # here to its measured range so a regression shows.
+    # through 150 CG steps that gives an image NRMSE anywhere from 8e-5 to
+    # 3.4e-3 on this problem, depending on the rounding details of the build,
+    # so BF16x3 is not held to the 1e-4 bar that FP32 and FP16x3 meet here.
+    # Held to its measured range so a regression shows.
     e = _admm256_full(mri.BF16X3)
-    assert 1e-4 < e <= 1e-2
+    assert e <= 1e-2
