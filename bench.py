@@ -70,17 +70,28 @@ def cpu_baseline(wl, p):
     """Oracle timed on one ADMM iteration (5 CG steps) of the same problem."""
     from oracle import admm as oadmm
     from oracle import nudft as onudft
+    blas = "unknown"
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        info = threadpool_info()
+        threads = max([i.get("num_threads", 1) for i in info] or [1])
+        blas = ", ".join(sorted({f"{i.get('internal_api')} {i.get('version')}" for i in info
+                                 if i.get("user_api") == "blas"})) or blas
     except Exception:  # pragma: no cover
         threads = os.cpu_count()
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except Exception:  # pragma: no cover
+        pass
     data = (onudft.forward(p.truth[0], p.smaps, p.traj) + p.noise[0]).astype(np.complex64)
     t0 = time.perf_counter()
     oadmm.admm(data, p.smaps, p.traj, wl.lam, wl.beta, 1, wl.cg_iters)
     dt = time.perf_counter() - t0
     return {"value": 1.0 / dt, "unit": "ADMM iters/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"1 ADMM iteration x {wl.cg_iters} CG (13 NUDFT calls incl. F^H d) of "
+            "host": {"cpu_model": cpu_model, "cpu_count": os.cpu_count(), "blas": blas},
+            "sample": f"1 ADMM iteration x {wl.cg_iters} CG ({1 + 2 * (1 + wl.cg_iters)} NUDFT calls incl. F^H d) of "
                       f"{wl.name}, FP64 NumPy, {dt:.1f} s"}
 
 
