@@ -4,6 +4,7 @@
     python -m paper_2006_14080_amd.profsum pmc <run_counter_collection.csv> --cmd "<command>"
     python -m paper_2006_14080_amd.profsum traffic <fetch.csv> <write.csv> --cmd "<command>" [--json out.json --key fp32]
     python -m paper_2006_14080_amd.profsum vecbw <run_kernel_stats.csv> --cmd "<command>" --npix N --coils C --planes P
+    python -m paper_2006_14080_amd.profsum busy <run_kernel_trace.csv> --cmd "<command>"
 
 ``vecbw`` turns the durations of the solver's memory-bound kernels into
 achieved bandwidth from their algorithmic bytes per pixel (listed in
@@ -166,9 +167,38 @@ def traffic(fetch_csv, write_csv):
     return out
 
 
+def busy(trace_csv, top):
+    """GPU busy fraction between the first and last NUDFT kernel of a kernel
+    trace (union of kernel intervals), and time per kernel in that window."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(r["Kernel_Name"]).split("(")[0])
+                for r in rows)
+    nud = [x for x in ev if x[2].startswith("nudft")]
+    t0, t1 = nud[0][0], nud[-1][1]
+    win = [x for x in ev if x[0] >= t0 and x[1] <= t1]
+    covered, cur_s, cur_e = 0, None, None
+    for s, e, _ in win:
+        if cur_e is None or s > cur_e:
+            if cur_e is not None:
+                covered += cur_e - cur_s
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    covered += cur_e - cur_s
+    agg = collections.defaultdict(lambda: [0, 0])
+    for s, e, k in win:
+        agg[k][0] += 1
+        agg[k][1] += e - s
+    out = [f"window {(t1 - t0) / 1e9:.2f} s, GPU busy {covered / 1e9:.2f} s ({covered / (t1 - t0):.1%})",
+           f"{'kernel':40s} {'calls':>6s} {'total_ms':>10s} {'avg_us':>10s}"]
+    for k, (c, t) in sorted(agg.items(), key=lambda x: -x[1][1])[:top]:
+        out.append(f"{k:40s} {c:6d} {t / 1e6:10.1f} {t / c / 1e3:10.1f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "pmc", "traffic", "vecbw"])
+    ap.add_argument("mode", choices=["stats", "pmc", "traffic", "vecbw", "busy"])
     ap.add_argument("csv")
     ap.add_argument("csv2", nargs="?")
     ap.add_argument("--cmd", required=True)
@@ -185,6 +215,12 @@ def main():
         print(f"# command: {a.cmd}")
         print(f"# pixels (all slices) = {a.npix}, coils = {a.coils}, adjoint partial images per slice = {a.planes}")
         for line in vecbw(a.csv, a.npix, a.coils, a.planes, a.copy_bytes):
+            print(line)
+        return 0
+    if a.mode == "busy":
+        print("# GPU busy time of a run from its rocprofv3 kernel trace")
+        print(f"# command: {a.cmd}")
+        for line in busy(a.csv, a.top):
             print(line)
         return 0
     if a.mode == "traffic":

@@ -217,6 +217,31 @@ def test_zero_and_nonfinite_inputs(prec):
     assert np.isnan(f).any() and np.isnan(a).any()
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_full_batch_launch_sampled(prec):
+    # The 32-slice 384x384 batch exactly as the batch benchmark launches it
+    # (one grouped launch per operator over all slices); the oracle checks
+    # sampled outputs of the first, a middle and the last slice.
+    wl = synth.SLICES384
+    rng = np.random.default_rng(75)
+    sm = synth.coil_maps(wl.nx, wl.ny, wl.nc)
+    tr = synth.radial_trajectory(wl.n_spokes, wl.n_readout)
+    img = synth.random_complex((wl.batch, wl.ny, wl.nx), 76)
+    dat = synth.random_complex((wl.batch, wl.nc, wl.nk), 77)
+    gs, gt = _gpu(sm), _gpu(tr)
+    f = mri.nudft_forward(_gpu(img), gs, gt, precision=prec)
+    a = mri.nudft_adjoint(_gpu(dat), gs, gt, wl.ny, wl.nx, precision=prec)
+    for b in (0, 17, wl.batch - 1):
+        coils = rng.integers(0, wl.nc, 32)
+        ks = rng.integers(0, wl.nk, 32)
+        got = f[b].cpu().numpy()[coils, ks]
+        assert rel(got, onudft.forward_samples(img[b], sm, tr, coils, ks)) <= TOL
+        rows = rng.integers(0, wl.ny, 32)
+        cols = rng.integers(0, wl.nx, 32)
+        got = a[b].cpu().numpy()[rows, cols]
+        assert rel(got, onudft.adjoint_pixels(dat[b], sm, tr, rows, cols)) <= TOL
+
+
 @pytest.mark.parametrize("nx,ny,batch", [(32, 32, 1), (7, 5, 3), (1, 9, 2), (300, 2, 1)])
 def test_tv_parity(nx, ny, batch):
     x = synth.random_complex((batch, ny, nx), 80)
