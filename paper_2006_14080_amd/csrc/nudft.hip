@@ -96,15 +96,15 @@ struct PolF32 {
         for (int kq = 0; kq < KC; kq += 4) {
             const floatx4 br = *reinterpret_cast<const floatx4*>(bre + kq);
             const floatx4 bi = *reinterpret_cast<const floatx4*>(bim + kq);
-            floatx4 av[NT];
+            // Row tile outer: each tile's A operand is read just before its eight
+            // MFMAs (re and im alternate, so dependent MFMAs are two apart).
 #pragma unroll
-            for (int t = 0; t < NT; ++t) av[t] = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
+            for (int t = 0; t < NT; ++t) {
+                const floatx4 av = *reinterpret_cast<const floatx4*>(ap + t * 32 * RS + kq);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t][j], br[j], acc_re[t], 0, 0, 0);
-                    acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[t][j], bi[j], acc_im[t], 0, 0, 0);
+                for (int j = 0; j < 4; ++j) {
+                    acc_re[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], br[j], acc_re[t], 0, 0, 0);
+                    acc_im[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[j], bi[j], acc_im[t], 0, 0, 0);
                 }
             }
         }
