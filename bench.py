@@ -1,7 +1,7 @@
 """Benchmark: ADMM-TV reconstruction throughput on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|bf16x3|fp16x3]
-                    [--workload admm256|slices384|serve]
+                    [--workload admm256|slices384|table1_1024x512|serve]
 
 One step = one full admm_solve of the 256x256, 8-coil, 64x512-sample radial
 problem (30 ADMM iterations x 5 CG steps: 1 + 2*30*6 = 361 NUDFT calls),
@@ -23,6 +23,11 @@ Other workloads (one JSON line each):
 
 * slices384 -- 32 slices of 384x384, 16 coils, 128x768 samples in one batched
   solve; one step = one ADMM iteration (5 CG) over the whole batch;
+* table1_1024x512 -- the large-image case of Sec. VI (1024x512 grid, 12
+  coils, 101x1024 samples per coil) with the Table I parameters: relative
+  tolerance 1e-4 over at most 5 ADMM iterations, CG absolute tolerance 1e-6
+  over at most 20 steps, both evaluated on the device; one step = one whole
+  reconstruction, reported in seconds;
 * serve -- a Poisson stream of mixed-shape requests (128/256/384 pixels,
   4-32 coils, 32-128 spokes x 2N, 30 ADMM x 5 CG) replayed in wall-clock time
   against the request server; reports p50/p99 latency and recons/s.
@@ -54,7 +59,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp16x3"], default="fp32")
-    ap.add_argument("--workload", choices=["admm256", "slices384", "serve"], default="admm256")
+    ap.add_argument("--workload", choices=["admm256", "slices384", "table1_1024x512", "serve"],
+                    default="admm256")
     ap.add_argument("--requests", type=int, default=24, help="serve: requests in the replayed stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: mean arrival rate (req/s)")
     ap.add_argument("--slots", type=int, default=8, help="serve: concurrent slots")
@@ -146,6 +152,65 @@ def bench_slices(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_table1_large(args):
+    """1024x512 / 12-coil reconstruction with the Table I stopping rules: seconds per solve."""
+    import torch
+    from paper_2006_14080_amd import mri, synth
+
+    prec = mri.PRECISIONS[args.precision]
+    wl = synth.TABLE1_1024x512
+    p = synth.make_problem(wl)
+    dev = torch.device("cuda:0")
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    sm, tr, truth = g(p.smaps), g(p.traj), g(p.truth)
+    data = mri.nudft_forward(truth, sm, tr, precision=mri.FP32)
+    data += g(p.noise.astype(np.complex64))
+    torch.cuda.synchronize()
+    params = mri.AdmmParams(wl.lam, wl.beta, wl.admm_iters, wl.cg_iters, rtol=wl.rtol, atol=wl.atol,
+                            precision=prec)
+    solver = mri.AdmmSolver(mri.shape_of((1, wl.ny, wl.nx), sm, tr), params, device=dev)
+    out = torch.empty((1, wl.ny, wl.nx), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        solver.solve(sm, tr, data, out=out)
+    torch.cuda.synchronize()
+    times, stats = [], []
+    for i in range(max(1, args.steps)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        solver.solve(sm, tr, data, out=out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+        stats.append(solver.stats()[0])
+        print(f"[table1_1024x512] solve {i + 1}: {times[-1]:.3f} s", file=sys.stderr, flush=True)
+    st = stats[-1]
+    if st["status"] != 0:
+        raise RuntimeError(f"solve failed: {st}")
+    calls = 1 + 2 * (st["admm_iters"] + st["cg_steps"])
+    s_solve = float(np.mean(times))
+    got = out[0].cpu().numpy().astype(np.complex128)
+    truth0 = p.truth[0].astype(np.complex128)
+    rec = {
+        "metric": "seconds per 1024x512 reconstruction (12 coils, 101x1024 radial samples, Table I stopping rules)",
+        "value": s_solve, "unit": "s", "n_gpus": 1, "steps": len(times), "warmup": args.warmup,
+        "ms_per_step": 1e3 * s_solve, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[args.precision],
+        "data": "synthetic (seeded ellipse phantom, Gaussian coil maps, golden-angle radial trajectory, "
+                "k-space data F(phantom) formed on the GPU plus complex Gaussian noise 1e-3)",
+        "config": {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "coils": wl.nc, "spokes": wl.n_spokes,
+                   "readout": wl.n_readout, "admm_max": wl.admm_iters, "cg_max": wl.cg_iters,
+                   "lambda": wl.lam, "beta": wl.beta, "rtol": wl.rtol, "atol": wl.atol,
+                   "precision": args.precision},
+        "admm_iters_run": int(st["admm_iters"]), "cg_steps_run": int(st["cg_steps"]),
+        "nudft_calls": calls,
+        "fp32_equiv_tflops": wl.nudft_flop * calls / s_solve / 1e12,
+        "solve_s_all": times,
+        "image_nrmse_vs_phantom": float(np.linalg.norm(got - truth0) / np.linalg.norm(truth0)),
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def bench_serve(args):
     """Mixed-shape request stream through the continuous-batching server."""
     import torch
@@ -196,6 +261,8 @@ def main():
         sys.exit(2)
     if args.workload == "slices384":
         return bench_slices(args)
+    if args.workload == "table1_1024x512":
+        return bench_table1_large(args)
     if args.workload == "serve":
         return bench_serve(args)
     import torch

@@ -2,6 +2,7 @@
 
     python -m paper_2006_14080_amd.profile_driver [fp32|bf16x3|fp16x3] [repeats]
     python -m paper_2006_14080_amd.profile_driver vec SLICES
+    python -m paper_2006_14080_amd.profile_driver shard PRECISION [repeats]
 
 The first form calls nudft_forward and nudft_adjoint at the 256x256 / 8-coil /
 64x512-sample shape `repeats` times, then copies a 256 MiB buffer twice (a
@@ -14,6 +15,12 @@ solver's memory-bound kernels work on multi-GB arrays (far beyond the 256 MB
 Infinity Cache), then copies 1 GiB three times (the plain-copy reference);
 it prints the pixel count and partial-image count that `profsum vecbw`
 needs.
+
+The third times (HIP events on the calling stream) nudft_forward and
+nudft_adjoint on one GPU's share of a k-space decomposition over 8 GPUs
+(Sec. IV-A: every coil's samples [0, nk/8)) next to the whole problem, at
+the 256x256 / 8-coil benchmark shape and at the 1024x512 / 12-coil /
+101x1024-sample shape of Sec. VI, and prints one line per case.
 """
 import sys
 
@@ -52,9 +59,52 @@ def vector_sweep(slices: int):
     print(f"profile driver done: npix={slices * n * n} coils={nc} planes=1", flush=True)
 
 
+def _time_ms(fn, repeats: int) -> float:
+    # Calls enqueued back to back between two events (the host stays ahead of
+    # the GPU), so the figure is device time per call, not host launch gaps.
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(repeats):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / repeats
+
+
+def shard_timings(prec: int, repeats: int, parts: int = 8):
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    name = mri.PRECISION_NAMES[prec]
+    for wl in (synth.ADMM256, synth.TABLE1_1024x512):
+        img = g(synth.ellipse_phantom(wl.nx, wl.ny, wl.seed)[None])
+        sm = g(synth.coil_maps(wl.nx, wl.ny, wl.nc))
+        tr_full = synth.radial_trajectory(wl.n_spokes, wl.n_readout)
+        dat_full = synth.random_complex((1, wl.nc, wl.nk), 1)
+        lo, hi = synth.kspace_shards(wl.nk, parts)[0]
+        for label, tr, dat in (("whole", tr_full, dat_full),
+                               (f"shard 1/{parts}", tr_full[lo:hi], dat_full[:, :, lo:hi])):
+            gt, gd = g(tr), g(dat)
+            nk = tr.shape[0]
+            y = torch.empty((1, wl.nc, nk), dtype=torch.complex64, device="cuda")
+            x = torch.empty((1, wl.ny, wl.nx), dtype=torch.complex64, device="cuda")
+            fwd = lambda: mri.nudft_forward(img, sm, gt, precision=prec, out=y)
+            adj = lambda: mri.nudft_adjoint(gd, sm, gt, wl.ny, wl.nx, precision=prec, out=x)
+            fwd(), adj()
+            tf, ta = _time_ms(fwd, repeats), _time_ms(adj, repeats)
+            flop = 8.0 * nk * wl.nx * wl.ny * wl.nc
+            print(f"{name:7s} {wl.nx}x{wl.ny} c{wl.nc} nk={nk:6d} {label:9s} "
+                  f"fwd {tf:8.3f} ms {flop / tf / 1e9:6.1f} TFLOP/s   "
+                  f"adj {ta:8.3f} ms {flop / ta / 1e9:6.1f} TFLOP/s", flush=True)
+    print("profile driver done", flush=True)
+
+
 def main(argv):
     if len(argv) > 1 and argv[1] == "vec":
         vector_sweep(int(argv[2]))
+        return
+    if len(argv) > 1 and argv[1] == "shard":
+        shard_timings(mri.PRECISIONS[argv[2]], int(argv[3]) if len(argv) > 3 else 5)
         return
     prec = mri.PRECISIONS[argv[1]] if len(argv) > 1 else mri.FP32
     n = int(argv[2]) if len(argv) > 2 else 2

@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -177,6 +177,19 @@ INVDFT128x64 = Workload("inverse_dft_128x64_c12_r101x128", 128, 64, 12, 101, 128
                         0.0, 1.0, 0, 0, seed=606)
 TABLE1_128x64 = Workload("admm_tv_table1_128x64_c12_r13x128", 128, 64, 12, 13, 128,
                          1e-7, 1.0, 5, 20, seed=707, rtol=1e-4, atol=1e-6)
+# The large-image scaling case of Sec. VI: a 1024 x 512 grid, 12 coils,
+# 103,424 samples per coil (101 spokes x 1024 samples after x8
+# undersampling), Table I parameters.
+TABLE1_1024x512 = Workload("admm_tv_table1_1024x512_c12_r101x1024", 1024, 512, 12, 101, 1024,
+                           1e-7, 1.0, 5, 20, seed=808, rtol=1e-4, atol=1e-6)
+
+
+def kspace_shards(nk: int, parts: int) -> List[Tuple[int, int]]:
+    """Contiguous sample ranges [lo, hi) splitting nk samples into `parts`
+    near-equal pieces (the k-space decomposition of Sec. IV-A, where each
+    core holds one range of every coil's samples)."""
+    bounds = [nk * p // parts for p in range(parts + 1)]
+    return list(zip(bounds[:-1], bounds[1:]))
 
 
 @dataclasses.dataclass
