@@ -96,10 +96,10 @@ enum { MRI_OP_FORWARD = 0, MRI_OP_ADJOINT = 1, MRI_OP_ADMM = 2 };
  *   precision: MRI_FP32, MRI_BF16X3 or MRI_FP16X3.
  *   ws/ws_bytes: workspace of at least mri_workspace_bytes(shape,
  *   MRI_OP_FORWARD, NULL) bytes; it receives the coil-weighted images
- *   s (.) x (rows padded to a multiple of 8 pixels): 8 B per coil pixel
- *   in FP32, 12 B in the split forms, which store them already split into
- *   16-bit high/low parts in the matrix cores' operand order (MRI_FP16X3
- *   adds one float scale per row).
+ *   s (.) x (rows padded to a multiple of 8 pixels): 8 B per coil pixel,
+ *   in FP32 or, in the split forms, already split into 16-bit high and low
+ *   parts in the matrix cores' operand order (MRI_FP16X3 adds one float
+ *   scale per row).
  * Errors: MRI_EINVAL, MRI_ENOTSUP, MRI_ENOMEM, MRI_EHIP.
  */
 int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps,

@@ -69,17 +69,19 @@ __host__ __device__ inline int fwd_padded_rows(int ny) {
     const int prows = 2 * fwd_nt(ny) * 32;
     return (ny + prows - 1) / prows * prows;
 }
-// (slice, coil, K-step, row) units of the split (16-bit) pre-pass; 96 bytes each.
+// (slice, coil, K-step, row) units of the split (16-bit) pre-pass: the hi and
+// lo chunks of both lane halves, 16 bytes each.
+constexpr int kSplitUnitBytes = 64;
 __host__ __device__ inline int64_t fwd_split_units(int nx, int ny, int nc, int nb) {
     return (int64_t)nb * nc * ((nx + kKStep - 1) / kKStep) * fwd_padded_rows(ny);
 }
 // Split-FP16 form: inverse row scales, float [nb][nc][padded rows], stored
-// right after the 96-byte units (16-byte aligned).
+// right after the units (16-byte aligned).
 __host__ __device__ inline int64_t fwd_rowscale_floats(int ny, int nc, int nb) {
     return (int64_t)nb * nc * fwd_padded_rows(ny);
 }
 __host__ __device__ inline float* fwd_rowscale(float2* wimg, int nx, int ny, int nc, int nb) {
-    return reinterpret_cast<float*>(reinterpret_cast<char*>(wimg) + 96 * fwd_split_units(nx, ny, nc, nb));
+    return reinterpret_cast<float*>(reinterpret_cast<char*>(wimg) + kSplitUnitBytes * fwd_split_units(nx, ny, nc, nb));
 }
 // Row tiles per wave of the adjoint: coils run in even groups of 2 * adj_nt.
 __host__ __device__ inline int adj_nt(int nc) {

@@ -113,17 +113,19 @@ struct PolF32 {
 
 // Split products (Sec. II-A "decomposition and accumulation"): each FP32
 // value a = hi + lo with hi = T(a), lo = T(a - hi) (round to nearest even) for
-// a 16-bit type T; a real product a b is formed as hi_a hi_b + hi_a lo_b +
-// lo_a hi_b with FP32 accumulation.  v_mfma_f32_32x32x16_{bf16,f16} take 8
-// K-slots per lane half; the six products of a complex K value for one
-// accumulator occupy six slots, ordered so that every 32-bit word is one
-// converted (re, im) pair and needs no repacking:
-//   A    : [ArH, AiH | ArL, AiL | ArH, AiH]
-//   B_re : [BrH, -BiH | BrH, -BiH | BrL, -BiL]   -> Ar Br - Ai Bi
-//   B_im : [BiH, BrH | BiH, BrH | BiL, BrL]      -> Ar Bi + Ai Br
-// Lane half h takes complex K values 4h..4h+3 (12 words = 3 instructions),
-// so 8 complex K values cost 3 MFMAs per accumulator with no idle slot.
-// LDS keeps every 16-byte operand chunk ready: A [h][m][row], B [var][h][m][col].
+// a 16-bit type T; a real product a b is formed as hi_a hi_b + lo_a hi_b +
+// hi_a lo_b with FP32 accumulation.  v_mfma_f32_32x32x16_{bf16,f16} take 8
+// K-slots per lane half: lane half h holds complex K values 4h..4h+3 as four
+// 32-bit words, each one converted (re, im) pair, so no word is repacked.
+// A 16-byte chunk holds one part (hi or lo) of those four values:
+//   A    : (ArH, AiH) x4   or  (ArL, AiL) x4
+//   B_re : (BrH, -BiH) x4  or  (BrL, -BiL) x4   -> Ar Br - Ai Bi
+//   B_im : (BiH, BrH) x4   or  (BiL, BrL) x4    -> Ar Bi + Ai Br
+// and the three products of 8 complex K values are three MFMAs per
+// accumulator: (A hi, B hi), (A lo, B hi), (A hi, B lo).  Each part is stored
+// and read from LDS once (two chunks per lane half instead of three, so a
+// third less LDS traffic than a slot order that repeats hi words within a
+// K value); LDS holds A [h][part][row], B [var][h][part][col].
 //
 // T = bf16 (the paper's form): 8 significant bits per part, so hi + lo holds
 // about 16 bits of each operand; it needs no scaling (bf16 has the FP32
@@ -145,8 +147,10 @@ struct PolSplit {
     static constexpr bool kPresplitA = true;         // forward A pre-split into operand chunks once per call
     static constexpr bool kScaled = Scaled;
     static constexpr float kBScale = Scaled ? 16384.0f : 1.0f;   // phases (|e| <= 1) -> [-2^14, 2^14]
-    static constexpr int kABytes = 2 * 3 * kRows * 16;
-    static constexpr int kBBytes = 2 * 2 * 3 * 64 * 16;
+    static constexpr int kChunks = 4;                // 16-byte chunks per row and K-step: (lane half, part)
+    static constexpr int kABytes = kChunks * kRows * 16;
+    static constexpr int kBBytes = 2 * kChunks * 64 * 16;
+    static_assert(kChunks * 16 == kSplitUnitBytes, "pre-split unit size");
 
     // (hi, lo) words of the pair (a, b): hi = [T(a), T(b)], lo = [T(a - hi_a), T(b - hi_b)].
     struct Words {
@@ -177,72 +181,70 @@ struct PolSplit {
     }
     __device__ __forceinline__ static floatx16 mfma(vec8 a, vec8 b, floatx16 c);
 
-    // One row of A (K values 0..KC-1) as six 16-byte chunks; chunk (h, m) of
-    // row r sits at ((h*3+m)*rows + r)*16.
+    // One row of A (K values 0..KC-1) as four 16-byte chunks; chunk (h, part)
+    // of row r sits at ((h*2+part)*rows + r)*16.
     __device__ __forceinline__ static void store_a_rows(char* st, int row, int rows, const float2 (&v)[KC]) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            uint32_t w[12];
+            uint32_t hi[4], lo[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const Words p = split2(v[4 * h + q].x, v[4 * h + q].y);
-                w[3 * q] = p.hi;
-                w[3 * q + 1] = p.lo;
-                w[3 * q + 2] = p.hi;
+                hi[q] = p.hi;
+                lo[q] = p.lo;
             }
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const u32x4 c = {w[4 * m], w[4 * m + 1], w[4 * m + 2], w[4 * m + 3]};
-                *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 3 + m) * rows + row) * 16) = c;
-            }
+            *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 2) * rows + row) * 16) = u32x4{hi[0], hi[1], hi[2], hi[3]};
+            *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 2 + 1) * rows + row) * 16) = u32x4{lo[0], lo[1], lo[2], lo[3]};
         }
     }
     __device__ __forceinline__ static void store_a(char* st, int row, const float2 (&v)[KC]) {
         store_a_rows(st, row, kRows, v);
     }
-    // B column col, complex K values kp and kp+1 (kp even): six words of each
-    // variant, i.e. words 3(kp&3) .. 3(kp&3)+5 of the half's twelve.
+    // B column col, complex K values kp and kp+1 (kp even): words kp&3 and
+    // (kp&3)+1 of the hi and lo chunks of both variants.
     __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
         const int h = kp >> 2;
         const Words r0 = split2(e0.x * kBScale, -e0.y * kBScale);   // [Br, -Bi]
         const Words r1 = split2(e1.x * kBScale, -e1.y * kBScale);
-        const uint32_t wre[6] = {r0.hi, r0.hi, r0.lo, r1.hi, r1.hi, r1.lo};
-        const uint32_t wim[6] = {rot(r0.hi), rot(r0.hi), rot(r0.lo), rot(r1.hi), rot(r1.hi), rot(r1.lo)};
-#pragma unroll
-        for (int var = 0; var < 2; ++var) {
-            const uint32_t* w = var == 0 ? wre : wim;
-            char* base = st + (((var * 2 + h) * 3) * 64 + col) * 16;
-            if ((kp & 3) == 0) {
-                // words 0..5: chunk 0 whole, first half of chunk 1
-                *reinterpret_cast<u32x4*>(base) = u32x4{w[0], w[1], w[2], w[3]};
-                *reinterpret_cast<u32x2*>(base + 64 * 16) = u32x2{w[4], w[5]};
-            } else {
-                // words 6..11: second half of chunk 1, chunk 2 whole
-                *reinterpret_cast<u32x2*>(base + 64 * 16 + 8) = u32x2{w[0], w[1]};
-                *reinterpret_cast<u32x4*>(base + 2 * 64 * 16) = u32x4{w[2], w[3], w[4], w[5]};
-            }
-        }
+        char* re = st + ((h * 2) * 64 + col) * 16 + (kp & 3) * 4;
+        char* im = re + 2 * 2 * 64 * 16;
+        *reinterpret_cast<u32x2*>(re) = u32x2{r0.hi, r1.hi};
+        *reinterpret_cast<u32x2*>(re + 64 * 16) = u32x2{r0.lo, r1.lo};
+        *reinterpret_cast<u32x2*>(im) = u32x2{rot(r0.hi), rot(r1.hi)};
+        *reinterpret_cast<u32x2*>(im + 64 * 16) = u32x2{rot(r0.lo), rot(r1.lo)};
     }
     template <int NT>
     __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
                                                int ntile, floatx16 (&acc_re)[NT], floatx16 (&acc_im)[NT]) {
         const int h = lane >> 5, l32 = lane & 31;
-        const char* bre = b + ((h * 3) * 64 + bcol0 + l32) * 16;
-        const char* bim = b + (((2 + h) * 3) * 64 + bcol0 + l32) * 16;
-        const char* ap = a + ((h * 3) * kRows + arow0 + l32) * 16;
+        const char* bre = b + ((h * 2) * 64 + bcol0 + l32) * 16;
+        const char* bim = bre + 2 * 2 * 64 * 16;
+        const char* ap = a + ((h * 2) * kRows + arow0 + l32) * 16;
         if (__builtin_amdgcn_readfirstlane(ntile) == 0) return;   // see PolF32::mma
+        // (A hi, B hi), (A lo, B hi), (A hi, B lo); re and im alternate, so
+        // dependent MFMAs are 2 NT apart.
+        const vec8 brh = *reinterpret_cast<const vec8*>(bre);
+        const vec8 bih = *reinterpret_cast<const vec8*>(bim);
+        vec8 ah[NT];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const vec8 br = *reinterpret_cast<const vec8*>(bre + m * 64 * 16);
-            const vec8 bi = *reinterpret_cast<const vec8*>(bim + m * 64 * 16);
-            vec8 av[NT];
+        for (int t = 0; t < NT; ++t) ah[t] = *reinterpret_cast<const vec8*>(ap + t * 32 * 16);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) av[t] = *reinterpret_cast<const vec8*>(ap + (m * kRows + t * 32) * 16);
+        for (int t = 0; t < NT; ++t) {
+            acc_re[t] = mfma(ah[t], brh, acc_re[t]);
+            acc_im[t] = mfma(ah[t], bih, acc_im[t]);
+        }
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                acc_re[t] = mfma(av[t], br, acc_re[t]);
-                acc_im[t] = mfma(av[t], bi, acc_im[t]);
-            }
+        for (int t = 0; t < NT; ++t) {
+            const vec8 al = *reinterpret_cast<const vec8*>(ap + (kRows + t * 32) * 16);
+            acc_re[t] = mfma(al, brh, acc_re[t]);
+            acc_im[t] = mfma(al, bih, acc_im[t]);
+        }
+        const vec8 brl = *reinterpret_cast<const vec8*>(bre + 64 * 16);
+        const vec8 bil = *reinterpret_cast<const vec8*>(bim + 64 * 16);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            acc_re[t] = mfma(ah[t], brl, acc_re[t]);
+            acc_im[t] = mfma(ah[t], bil, acc_im[t]);
         }
     }
 };
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(256) void k_coil_weight_bf16(const NudftTable tab) 
         v[j] = (y < it.ny && x < it.nx) ? cmul(sm[x], im[x]) : make_float2(0.f, 0.f);
     }
     // Chunk planes of a K-step are yp rows long here (kRows in LDS).
-    char* base = reinterpret_cast<char*>(it.wimg) + (((int64_t)bg * nsteps + s) * 6 * yp) * 16;
+    char* base = reinterpret_cast<char*>(it.wimg) + (((int64_t)bg * nsteps + s) * PolBF16::kChunks * yp) * 16;
     PolBF16::store_a_rows(base, y, yp, v);
 }
 
@@ -405,7 +407,7 @@ __global__ __launch_bounds__(256) void k_coil_weight_f16(const NudftTable tab) {
         row_step(s, v);
 #pragma unroll
         for (int j = 0; j < KC; ++j) v[j] = cscale(v[j], sc);
-        PolF16::store_a_rows(wbase + (((int64_t)bg * nsteps + s) * 6 * yp) * 16, y, yp, v);
+        PolF16::store_a_rows(wbase + (((int64_t)bg * nsteps + s) * PolF16::kChunks * yp) * 16, y, yp, v);
     }
     if (lane == 0) fwd_rowscale(it.wimg, it.nx, it.ny, it.nc, it.nb)[(int64_t)bg * yp + y] = ldexpf(1.0f, -se);
 }
@@ -507,7 +509,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         const float rmask = row_ok ? 1.0f : 0.0f;
         const int yp = fwd_padded_rows(ny);
         const char* wsplit = reinterpret_cast<const char*>(it.wimg) +
-                             ((int64_t)(b * nc + g) * nsteps * 6 * yp + (int64_t)min(yrow, yp - 1)) * 16;
+                             ((int64_t)(b * nc + g) * nsteps * kSplitUnitBytes / 16 * yp + (int64_t)min(yrow, yp - 1)) * 16;
         float4 pre[KC / 2];
 
         // FP32: global -> registers (prefetched one step ahead) -> LDS planes.
@@ -518,9 +520,9 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             if constexpr (P::kPresplitA) {
                 const int st = s & 1;
                 char* dst = sA0 + st * P::kABytes + wave * 64 * 16;   // wave-uniform
-                const char* g = wsplit + (int64_t)s * 6 * yp * 16;
+                const char* g = wsplit + (int64_t)s * P::kChunks * yp * 16;
 #pragma unroll
-                for (int c = 0; c < 6; ++c)
+                for (int c = 0; c < P::kChunks; ++c)
                     __builtin_amdgcn_global_load_lds(g + (int64_t)c * yp * 16, dst + c * kRows * 16, 16, 0, 0);
             } else {
 #pragma unroll
@@ -885,7 +887,12 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
     // 1024 keeps 1024 samples per split.
     const int64_t target = 1024;
     int64_t s = ceil_div(target, tps);
-    const int64_t smax = std::max<int64_t>(1, nk / 512);   // keep >= 512 samples per split
+    // At least 256 samples per split: short sample ranges (one GPU's share of
+    // a k-space split, 4096 samples per coil at 256^2) then still fill the
+    // GPU; 512 left half of it idle there (adjoint 9 % slower in FP32, 30 %
+    // in the split forms), and 128 spends more on each workgroup's coil
+    // combine and on the partial images than it gains.
+    const int64_t smax = std::max<int64_t>(1, nk / 256);
     if (s > smax) s = smax;
     if (s < 1) s = 1;
     int64_t per = ceil_div(ceil_div(nk, s), KC) * KC;

@@ -39,7 +39,7 @@ int check_params(const mri_admm_params* p) {
 
 size_t forward_ws(const mri_shape& s) {
     const size_t f32 = sizeof(float2) * (size_t)fwd_wimg_elems(s.nx, s.ny, s.ncoils, s.batch);
-    const size_t bf = 96 * (size_t)fwd_split_units(s.nx, s.ny, s.ncoils, s.batch) +
+    const size_t bf = kSplitUnitBytes * (size_t)fwd_split_units(s.nx, s.ny, s.ncoils, s.batch) +
                       sizeof(float) * (size_t)fwd_rowscale_floats(s.ny, s.ncoils, s.batch);
     return ws_align(f32 > bf ? f32 : bf);
 }

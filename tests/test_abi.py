@@ -56,9 +56,9 @@ def test_workspace_sizes(lib):
     sh = mri.make_shape(256, 256, 8, 32768)
     p = mri.AdmmParams(1e-3, 1.0, 30, 5).c()
     # forward: the coil-weighted image, rows padded to a multiple of 8; the
-    # split forms keep it pre-split (hi/lo of re and im: 12 B per element),
-    # FP16x3 with one float scale per row
-    assert mri.workspace_bytes(sh, mri.OP_FORWARD) == 8 * 256 * 256 * 12 + 4 * 8 * 256
+    # split forms keep it pre-split (16-bit hi and lo of re and im: 8 B per
+    # element, as in FP32), FP16x3 with one float scale per row
+    assert mri.workspace_bytes(sh, mri.OP_FORWARD) == 8 * 256 * 256 * 8 + 4 * 8 * 256
     adj = mri.workspace_bytes(sh, mri.OP_ADJOINT)
     assert adj >= 256 * 256 * 8 and adj % 256 == 0
     total = mri.workspace_bytes(sh, mri.OP_ADMM, p)
