@@ -77,7 +77,22 @@ def pmc(path):
             if counters.get("SQ_INSTS_MFMA"):
                 extra += f", {counters.get('SQ_INSTS_VALU', 0.0) / counters['SQ_INSTS_MFMA']:.1f} VALU per MFMA"
             out.append(extra)
+        # Derived: LDS use.  GRBM_GUI_ACTIVE is reported summed over the XCDs,
+        # so the GPU's cycles in the dispatch are its value / XCDS; LDS counters
+        # are summed over all CUs.
+        if "SQ_LDS_IDX_ACTIVE" in counters and counters.get("GRBM_GUI_ACTIVE"):
+            cyc = counters["GRBM_GUI_ACTIVE"] / n / XCDS
+            cu_cyc = cyc * CUS
+            rd = counters.get("SQ_INSTS_LDS_LOAD_BANDWIDTH", 0.0) / n * 64
+            wr = counters.get("SQ_INSTS_LDS_STORE_BANDWIDTH", 0.0) / n * 64
+            out.append(f"  -> LDS busy {counters['SQ_LDS_IDX_ACTIVE'] / n / cu_cyc:.1%} of cycles, "
+                       f"bank-conflict stalls {counters.get('SQ_LDS_BANK_CONFLICT', 0.0) / n / cu_cyc:.1%}, "
+                       f"ds_read {rd / 1e6:.0f} MB + ds_write {wr / 1e6:.0f} MB per dispatch "
+                       f"= {(rd + wr) / cu_cyc:.1f} B/clk per CU")
     return out
+
+
+XCDS, CUS = 8, 256      # MI355X
 
 
 # Algorithmic bytes per pixel (complex64 = 8 B) of each memory-bound kernel:
