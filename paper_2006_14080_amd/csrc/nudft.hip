@@ -35,6 +35,8 @@ namespace mri {
 namespace {
 
 constexpr int kThreads = 256;             // 4 waves: 2 (rows) x 2 (cols)
+constexpr int kThreads8 = 512;            // split-form adjoint: 8 waves, 2 (rows) x 4 (cols)
+constexpr int kAdjCols8 = 128;            // its x columns per tile
 constexpr int kNT = 4;                    // 32-row MFMA tiles per wave
 constexpr int kRows = 2 * kNT * 32;       // GEMM rows per pass (256)
 constexpr int KC = kKStep;                // complex K values per stage (8)
@@ -61,6 +63,7 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
 // plane Ar / Br / Bi, lanes 32-63 read Ai / -Bi / Br, four K values per read.
 struct PolF32 {
     static constexpr bool kPrioritiseMfma = false;   // measured: no gain (MFMA-bound already)
+    static constexpr bool kInterleave = false;       // FP32 MFMA and VALU do not execute at once (counters)
     static constexpr bool kPresplitA = false;        // forward A staged from the FP32 coil-weighted image
     static constexpr bool kScaled = false;
     static constexpr float kBScale = 1.0f;
@@ -144,6 +147,7 @@ struct PolSplit {
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     static constexpr bool kPrioritiseMfma = true;    // measured: +5% on the VALU-heavy forward
+    static constexpr bool kInterleave = true;        // producers run between the MFMAs (mma_with)
     static constexpr bool kPresplitA = true;         // forward A pre-split into operand chunks once per call
     static constexpr bool kScaled = Scaled;
     static constexpr float kBScale = Scaled ? 16384.0f : 1.0f;   // phases (|e| <= 1) -> [-2^14, 2^14]
@@ -184,18 +188,20 @@ struct PolSplit {
     // One row of A (K values 0..KC-1) as four 16-byte chunks; chunk (h, part)
     // of row r sits at ((h*2+part)*rows + r)*16.
     __device__ __forceinline__ static void store_a_rows(char* st, int row, int rows, const float2 (&v)[KC]) {
+        store_a_half(st, row, rows, 0, v);
+        store_a_half(st, row, rows, 1, v + 4);
+    }
+    // Chunks (h, hi) and (h, lo) of one row: K values 4h..4h+3 from v[0..3].
+    __device__ __forceinline__ static void store_a_half(char* st, int row, int rows, int h, const float2* v) {
+        uint32_t hi[4], lo[4];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            uint32_t hi[4], lo[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const Words p = split2(v[4 * h + q].x, v[4 * h + q].y);
-                hi[q] = p.hi;
-                lo[q] = p.lo;
-            }
-            *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 2) * rows + row) * 16) = u32x4{hi[0], hi[1], hi[2], hi[3]};
-            *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 2 + 1) * rows + row) * 16) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+        for (int q = 0; q < 4; ++q) {
+            const Words p = split2(v[q].x, v[q].y);
+            hi[q] = p.hi;
+            lo[q] = p.lo;
         }
+        *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 2) * rows + row) * 16) = u32x4{hi[0], hi[1], hi[2], hi[3]};
+        *reinterpret_cast<u32x4*>(st + ((int64_t)(h * 2 + 1) * rows + row) * 16) = u32x4{lo[0], lo[1], lo[2], lo[3]};
     }
     __device__ __forceinline__ static void store_a(char* st, int row, const float2 (&v)[KC]) {
         store_a_rows(st, row, kRows, v);
@@ -203,22 +209,27 @@ struct PolSplit {
     // B column col, complex K values kp and kp+1 (kp even): words kp&3 and
     // (kp&3)+1 of the hi and lo chunks of both variants.
     __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
-        const int h = kp >> 2;
-        const Words r0 = split2(e0.x * kBScale, -e0.y * kBScale);   // [Br, -Bi]
-        const Words r1 = split2(e1.x * kBScale, -e1.y * kBScale);
-        char* re = st + ((h * 2) * 64 + col) * 16 + (kp & 3) * 4;
-        char* im = re + 2 * 2 * 64 * 16;
-        *reinterpret_cast<u32x2*>(re) = u32x2{r0.hi, r1.hi};
-        *reinterpret_cast<u32x2*>(re + 64 * 16) = u32x2{r0.lo, r1.lo};
-        *reinterpret_cast<u32x2*>(im) = u32x2{rot(r0.hi), rot(r1.hi)};
-        *reinterpret_cast<u32x2*>(im + 64 * 16) = u32x2{rot(r0.lo), rot(r1.lo)};
+        store_b_words<64>(st, col, kp, split_b(e0), split_b(e1));
     }
-    template <int NT>
+    // [Br, -Bi] words of one B value (phases carry the kBScale factor).
+    __device__ __forceinline__ static Words split_b(float2 e) { return split2(e.x * kBScale, -e.y * kBScale); }
+    // B stages hold BC columns: [var][h][part][col], 16 bytes per chunk.
+    template <int BC>
+    __device__ __forceinline__ static void store_b_words(char* st, int col, int kp, Words r0, Words r1) {
+        const int h = kp >> 2;
+        char* re = st + ((h * 2) * BC + col) * 16 + (kp & 3) * 4;
+        char* im = re + 2 * 2 * BC * 16;
+        *reinterpret_cast<u32x2*>(re) = u32x2{r0.hi, r1.hi};
+        *reinterpret_cast<u32x2*>(re + BC * 16) = u32x2{r0.lo, r1.lo};
+        *reinterpret_cast<u32x2*>(im) = u32x2{rot(r0.hi), rot(r1.hi)};
+        *reinterpret_cast<u32x2*>(im + BC * 16) = u32x2{rot(r0.lo), rot(r1.lo)};
+    }
+    template <int NT, int BC = 64>
     __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
                                                int ntile, floatx16 (&acc_re)[NT], floatx16 (&acc_im)[NT]) {
         const int h = lane >> 5, l32 = lane & 31;
-        const char* bre = b + ((h * 2) * 64 + bcol0 + l32) * 16;
-        const char* bim = bre + 2 * 2 * 64 * 16;
+        const char* bre = b + ((h * 2) * BC + bcol0 + l32) * 16;
+        const char* bim = bre + 2 * 2 * BC * 16;
         const char* ap = a + ((h * 2) * kRows + arow0 + l32) * 16;
         if (__builtin_amdgcn_readfirstlane(ntile) == 0) return;   // see PolF32::mma
         // (A hi, B hi), (A lo, B hi), (A hi, B lo); re and im alternate, so
@@ -239,12 +250,78 @@ struct PolSplit {
             acc_re[t] = mfma(al, brh, acc_re[t]);
             acc_im[t] = mfma(al, bih, acc_im[t]);
         }
-        const vec8 brl = *reinterpret_cast<const vec8*>(bre + 64 * 16);
-        const vec8 bil = *reinterpret_cast<const vec8*>(bim + 64 * 16);
+        const vec8 brl = *reinterpret_cast<const vec8*>(bre + BC * 16);
+        const vec8 bil = *reinterpret_cast<const vec8*>(bim + BC * 16);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             acc_re[t] = mfma(ah[t], brl, acc_re[t]);
             acc_im[t] = mfma(ah[t], bil, acc_im[t]);
+        }
+    }
+    // The same products with a producer interleaved: prod(i), i = 0..5, runs
+    // after each sixth of the MFMAs.  Scheduling fences keep each piece of
+    // vector work between two groups of matrix-core instructions, so the SIMD
+    // executes both at once instead of one burst after the other.  Every wave
+    // runs all its tiles (a wave without live rows works on rows the epilogue
+    // never reads): a skip branch would make the compiler copy the
+    // accumulators where the two paths meet.
+    //   kByTile false: the groups are (part, half of the tiles) and all
+    //     operands are read up front (the forward: fewer waits);
+    //   kByTile true: the MFMAs go tile by tile, (hi, hi), (lo, hi), (hi, lo)
+    //     with re and im alternating, and a tile's A operands are read one
+    //     group ahead, so only B and about two tiles of A are live (the
+    //     adjoint, whose producers hold more registers).
+    template <int NT, int BC, bool kByTile, class Prod>
+    __device__ __forceinline__ static void mma_with(const char* a, const char* b, int arow0, int bcol0, int lane,
+                                                    floatx16 (&acc_re)[NT], floatx16 (&acc_im)[NT], Prod&& prod) {
+        const int h = lane >> 5, l32 = lane & 31;
+        const char* bre = b + ((h * 2) * BC + bcol0 + l32) * 16;
+        const char* bim = bre + 2 * 2 * BC * 16;
+        const char* ap = a + ((h * 2) * kRows + arow0 + l32) * 16;
+        const vec8 bh[2] = {*reinterpret_cast<const vec8*>(bre), *reinterpret_cast<const vec8*>(bim)};
+        const vec8 bl[2] = {*reinterpret_cast<const vec8*>(bre + BC * 16),
+                            *reinterpret_cast<const vec8*>(bim + BC * 16)};
+        vec8 ah[NT], al[NT];
+        if constexpr (!kByTile) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                ah[t] = *reinterpret_cast<const vec8*>(ap + t * 32 * 16);
+                al[t] = *reinterpret_cast<const vec8*>(ap + (kRows + t * 32) * 16);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < 6; ++g) {
+            if constexpr (kByTile) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const int gt = (6 * t) / NT;          // group of tile t's first MFMA
+                    if ((g == 0 && gt <= 1) || (g > 0 && gt == g + 1)) {
+                        ah[t] = *reinterpret_cast<const vec8*>(ap + t * 32 * 16);
+                        al[t] = *reinterpret_cast<const vec8*>(ap + (kRows + t * 32) * 16);
+                    }
+                }
+#pragma unroll
+                for (int i = g * NT; i < (g + 1) * NT; ++i) {
+                    const int t = i / 6, part = (i % 6) / 2;
+                    const vec8 av = part == 1 ? al[t] : ah[t];
+                    if ((i & 1) == 0)
+                        acc_re[t] = mfma(av, part == 2 ? bl[0] : bh[0], acc_re[t]);
+                    else
+                        acc_im[t] = mfma(av, part == 2 ? bl[1] : bh[1], acc_im[t]);
+                }
+            } else {
+                const int part = g >> 1;
+                const int t0 = (g & 1) ? NT / 2 : 0, t1 = (g & 1) ? NT : NT / 2;
+#pragma unroll
+                for (int t = t0; t < t1; ++t) {
+                    const vec8 av = part == 1 ? al[t] : ah[t];
+                    acc_re[t] = mfma(av, part == 2 ? bl[0] : bh[0], acc_re[t]);
+                    acc_im[t] = mfma(av, part == 2 ? bl[1] : bh[1], acc_im[t]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            prod(g);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 };
@@ -451,6 +528,8 @@ __global__ __launch_bounds__(256) void k_adj_scale(const NudftTable tab) {
 
 // ---------------------------------------------------------------------------
 // Forward: tile = (slice, coil, 64 samples); rows = every y in passes of 256.
+// In the split forms the next B stage is produced between the MFMA groups of
+// the current one (mma_with); in FP32 it follows them.
 // ---------------------------------------------------------------------------
 template <class P, int NT>
 __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
@@ -516,6 +595,15 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         // Split-BF16: the pre-split chunks go global -> LDS directly
         // (global_load_lds_dwordx4: lane i of a wave lands at base + 16 i, and the
         // LDS chunk planes hold consecutive rows), issued one step ahead.
+        auto load_a_to = [&](int s, int st) {
+            if constexpr (P::kPresplitA) {
+                char* dst = sA0 + st * P::kABytes + wave * 64 * 16;   // wave-uniform
+                const char* g = wsplit + (int64_t)s * P::kChunks * yp * 16;
+#pragma unroll
+                for (int c = 0; c < P::kChunks; ++c)
+                    __builtin_amdgcn_global_load_lds(g + (int64_t)c * yp * 16, dst + c * kRows * 16, 16, 0, 0);
+            }
+        };
         auto load_a = [&](int s) {
             if constexpr (P::kPresplitA) {
                 const int st = s & 1;
@@ -565,20 +653,63 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         store_b(0, 0);
         wait_a();
         __syncthreads();
-        for (int s = 0; s < nsteps; ++s) {
-            const int cur = s & 1;
-            const bool more = s + 1 < nsteps;
-            if (more) load_a(s + 1);
-            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);   // MFMA burst ahead of the co-resident wave's VALU
-            P::template mma<NT>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32), wn * 32, lane, nvalid,
-                   acc_re, acc_im);
-            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
-            if (more) {
-                store_a(cur ^ 1);
-                store_b(cur ^ 1, s + 1);
+        if constexpr (P::kPresplitA) {
+            // Split forms: the next stage's B phases are produced in six pieces
+            // between the MFMA groups of this stage, branch-free (lanes past
+            // the last sample store zeros; the last step produces its own
+            // stage again into the idle buffer, where nothing reads it).
+            for (int s = 0; s < nsteps; ++s) {
+                const int cur = s & 1;
+                const int sn = s + 1 < nsteps ? s + 1 : s;
+                QuarterTurn qt;
+                SinCos sc;
+                float2 e0, e1;
+                typename P::Words r0, r1;
+                auto prod = [&](int piece) {
+                    if (piece == 0) {
+                        // The next A stage's copies start here, after this
+                        // stage's operand reads: issued before them, they would
+                        // make those reads wait for the copies to land.
+                        load_a_to(sn, cur ^ 1);
+                        qt = reduce_quarter_turns(fx4 * (double)(sn * KC - xh));
+                    } else if (piece == 1) {
+                        sc = sincos_octant(qt.th);
+                    } else if (piece == 2) {
+                        const SinCos r = rotate_quadrant(sc, qt.q);
+                        const float2 base = make_float2(r.c, -r.s);
+                        e0 = cmul(base, w0);
+                        e1 = cmul(base, w1);
+                    } else if (piece == 3) {
+                        e0 = p_ok ? e0 : make_float2(0.f, 0.f);
+                        e1 = p_ok ? e1 : make_float2(0.f, 0.f);
+                        r0 = P::split_b(e0);
+                    } else if (piece == 4) {
+                        r1 = P::split_b(e1);
+                    } else {
+                        P::template store_b_words<64>(sB0 + (cur ^ 1) * P::kBBytes, pc, pj, r0, r1);
+                    }
+                };
+                if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);
+                P::template mma_with<NT, 64, false>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32),
+                                                    wn * 32, lane, acc_re, acc_im, prod);
+                if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
+                wait_a();
+                __syncthreads();
             }
-            wait_a();
-            __syncthreads();
+        } else {
+            for (int s = 0; s < nsteps; ++s) {
+                const int cur = s & 1;
+                const bool more = s + 1 < nsteps;
+                if (more) load_a(s + 1);
+                P::template mma<NT>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32), wn * 32, lane,
+                                    nvalid, acc_re, acc_im);
+                if (more) {
+                    store_a(cur ^ 1);
+                    store_b(cur ^ 1, s + 1);
+                }
+                wait_a();
+                __syncthreads();
+            }
         }
 
         // Epilogue: sum_y T[y][k] Ey[k][y] over this pass's rows.  Rows of a
@@ -639,7 +770,9 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
 
 // ---------------------------------------------------------------------------
 // Adjoint: tile = (slice, split, 32 y rows, 64 x columns); GEMM rows are
-// (coil, y) for a group of 8 coils per pass.
+// (coil, y) for a group of 8 coils per pass.  Launched for the FP32 form,
+// whose matrix instructions do not run alongside vector work, so its
+// producers simply follow each MFMA burst; the split forms use nudft_adj8.
 // ---------------------------------------------------------------------------
 template <class P, int NT>
 __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
@@ -859,6 +992,275 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint of the split forms: 8 waves over a 32 y x 128 x pixel tile (one
+// workgroup per CU).  The GEMM rows are (coil, y) as in nudft_adj; doubling
+// the x extent lets every W = d conj(Ey) value feed twice the MFMAs, which
+// cuts the vector work per matrix instruction by about a quarter.  Each
+// thread forms half a W row (4 K values), two conj(Ex) phases and one
+// conj(Ey) phase per step (waves 4-7 evaluate the same conj(Ey) phases as
+// waves 0-3 and store them into the tile's padding column, so every wave does
+// the same work and the loop has no role branch).  Steps whose look-ahead
+// loads are whole steps run with the producers interleaved between the MFMA
+// groups; the split's last steps take a plain loop.
+// ---------------------------------------------------------------------------
+template <class P, int NT>
+__global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab) {
+    constexpr int BC = kAdjCols8;
+    constexpr int kBBytes8 = 2 * P::kChunks * BC * 16;
+    __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + kBBytes8)];
+    __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC + 2];   // conj(Ey); column KC takes duplicates
+    __shared__ float sUnscale[2 * kNT];
+    char* const sA0 = smem;
+    char* const sB0 = smem + 2 * P::kABytes;
+
+    const int tile = xcd_remap(blockIdx.x, tab.total_tiles);
+    const NudftItem& it = tab.it[find_item(tab, tile)];
+    const int nx = it.nx, ny = it.ny, nc = it.nc;
+    const int64_t nk = it.nk;
+    int local = tile - it.tile_begin;
+    const int nxb = (nx + BC - 1) / BC, nyb = (ny + kAdjRows - 1) / kAdjRows;
+    const int sp = local % it.ksplit;
+    local /= it.ksplit;
+    const int xb = local % nxb;
+    local /= nxb;
+    const int yb = local % nyb;
+    const int b = local / nyb;
+    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
+    const int x0 = xb * BC, y0 = yb * kAdjRows;
+    const int64_t npix = (int64_t)nx * ny;
+    const double* traj = it.traj + b * it.traj_bs;
+    const float2* sm = it.smaps + b * it.smaps_bs;
+    const float2* dat = it.data + (int64_t)b * nc * nk;
+    const int xh = nx / 2, yh = ny / 2;
+    const int64_t kbeg = (int64_t)sp * it.kper;
+    const int64_t kend = min(nk, kbeg + it.kper);
+    const int nsteps = (int)ceil_div(kend - kbeg, KC);
+    const int klast = (int)(kend - kbeg - 1);             // last sample of the split, relative
+    const double* trs = traj + 2 * kbeg;
+    const int32_t* aexp = nullptr;
+    if constexpr (P::kScaled) aexp = adj_scale_exp(it.part, nx, ny, nc, it.nb, it.ksplit);
+
+    // Producer roles.
+    const int ey = tid & 31, ek = (tid >> 5) & 7;        // E: (y, k); waves 4-7 duplicate 0-3
+    const int ecol = tid < 256 ? ek : KC;                // where this thread's E value goes
+    const int bx = tid & 127, bk = (tid >> 7) * 2;       // B: (x, k pair)
+    const int arow = tid & 255, ahalf = tid >> 8;        // A: row (coil, y), K half
+    const int ac = arow >> 5, ay = arow & 31;
+    const double yr = (double)(y0 + ey - yh);
+    const bool ey_ok = y0 + ey < ny;
+    const double xr = (double)(x0 + bx - xh);
+    const bool bx_ok = x0 + bx < nx;
+    const int xe = x0 + wn * 32 + l32;                   // epilogue column
+
+    constexpr int nt = NT;
+    constexpr int gsz = 2 * NT;
+    const int ncgroups = (nc + gsz - 1) / gsz;
+    for (int gi = 0, g0 = 0; g0 < nc; ++gi, g0 += gsz) {
+        const int ncg = min(gsz, nc - g0);
+        const int nvalid = max(0, min(nt, ncg - wm * nt));
+        // Rows of coils past the group's end read coil g0 and feed only
+        // accumulator tiles that the epilogue never reads.
+        const bool a_ok = ac < ncg;
+        const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk + kbeg;
+        float2 dreg[4];
+
+        float ascale = 1.0f;
+        if constexpr (P::kScaled) {
+            const int se = a_ok ? aexp[((int64_t)b * nc + g0 + ac) * it.ksplit + sp] : 0;
+            ascale = ldexpf(1.0f, se);
+            if (ay == 0 && ahalf == 0 && ac < gsz) sUnscale[ac] = ldexpf(1.0f, -se);
+        }
+
+        // d of this thread's 4 K values of step s (clamped to the split's
+        // last sample in the last step; those samples meet a zero E).
+        auto load_d = [&](int s) {
+            if (s * KC + KC - 1 <= klast) {
+                const float2* p = drow + s * KC + 4 * ahalf;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dreg[j] = p[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) dreg[j] = drow[min(s * KC + 4 * ahalf + j, klast)];
+            }
+        };
+        double tfx0, tfx1, tfy;
+        auto load_fx = [&](int s) {
+            const int k = s * KC + bk;
+            tfx0 = trs[2 * min(k, klast)];
+            tfx1 = trs[2 * min(k + 1, klast)];
+        };
+        auto load_fy = [&](int s) { tfy = trs[2 * min(s * KC + ek, klast) + 1]; };
+        auto gen_e = [&](int st, int s) {
+            const SinCos c = sincos_quarter_turns(tfy * kQuarterTurnsPerRad * yr);
+            const float m = (ey_ok && s * KC + ek <= klast) ? 1.f : 0.f;
+            sE[st][ey][ecol] = make_float2(c.c * m, c.s * m);
+        };
+        auto gen_b = [&](int st, int s) {
+            const int k = s * KC + bk;
+            const SinCos c0 = sincos_quarter_turns(tfx0 * kQuarterTurnsPerRad * xr);
+            const SinCos c1 = sincos_quarter_turns(tfx1 * kQuarterTurnsPerRad * xr);
+            const float m0 = (bx_ok && k <= klast) ? 1.f : 0.f;
+            const float m1 = (bx_ok && k + 1 <= klast) ? 1.f : 0.f;
+            P::template store_b_words<BC>(sB0 + st * kBBytes8, bx, bk,
+                                          P::split_b(make_float2(c0.c * m0, c0.s * m0)),
+                                          P::split_b(make_float2(c1.c * m1, c1.s * m1)));
+        };
+        // W of this thread's row and K half: d conj(Ey) (with the coil's scale).
+        auto gen_a = [&](int st, int est) {
+            float2 w[4];
+#pragma unroll
+            for (int j = 0; j < 4; j += 2) {
+                const float4 e2 = *reinterpret_cast<const float4*>(&sE[est][ay][4 * ahalf + j]);
+                w[j] = cmul(dreg[j], make_float2(e2.x, e2.y));
+                w[j + 1] = cmul(dreg[j + 1], make_float2(e2.z, e2.w));
+                if constexpr (P::kScaled) {
+                    w[j] = cscale(w[j], ascale);
+                    w[j + 1] = cscale(w[j + 1], ascale);
+                }
+            }
+            P::store_a_half(sA0 + st * P::kABytes, ac * 32 + ay, kRows, ahalf, w);
+        };
+
+        floatx16 acc_re[NT], acc_im[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            acc_re[t] = floatx16{0};
+            acc_im[t] = floatx16{0};
+        }
+        // Prologue: E(0), d(0) -> A(0), B(0); E(1), d(1) and the next
+        // trajectory values ready for the loop.
+        load_fy(0);
+        gen_e(0, 0);
+        load_d(0);
+        load_fx(0);
+        __syncthreads();
+        gen_a(0, 0);
+        gen_b(0, 0);
+        load_fx(1);
+        if (nsteps > 1) {
+            load_fy(1);
+            gen_e(1, 1);
+            load_d(1);
+        }
+        load_fy(2);
+        __syncthreads();
+        int s = 0;
+        for (; s < nsteps - 3; ++s) {
+            // Steady state: every look-ahead load is a whole step, no branch.
+            const int cur = s & 1;
+            float2 w[4];
+            QuarterTurn qb0, qb1, qe;
+            float2 e0, e1;
+            auto prod = [&](int piece) {
+                if (piece == 0) {                 // W(s+1), first two values
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        w[j] = cmul(dreg[j], sE[cur ^ 1][ay][4 * ahalf + j]);
+                        if constexpr (P::kScaled) w[j] = cscale(w[j], ascale);
+                    }
+                } else if (piece == 1) {          // W(s+1), last two values; store; d(s+2)
+#pragma unroll
+                    for (int j = 2; j < 4; ++j) {
+                        w[j] = cmul(dreg[j], sE[cur ^ 1][ay][4 * ahalf + j]);
+                        if constexpr (P::kScaled) w[j] = cscale(w[j], ascale);
+                    }
+                    P::store_a_half(sA0 + (cur ^ 1) * P::kABytes, ac * 32 + ay, kRows, ahalf, w);
+                    const float2* q = drow + (s + 2) * KC + 4 * ahalf;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) dreg[j] = q[j];
+                } else if (piece == 2) {          // conj(Ex) of step s+1: reductions; fx(s+2)
+                    qb0 = reduce_quarter_turns(tfx0 * kQuarterTurnsPerRad * xr);
+                    qb1 = reduce_quarter_turns(tfx1 * kQuarterTurnsPerRad * xr);
+                    const double* q = trs + 2 * ((s + 2) * KC + bk);
+                    tfx0 = q[0];
+                    tfx1 = q[2];
+                } else if (piece == 3) {          // polynomials, quadrants, masks
+                    const int k = (s + 1) * KC + bk;
+                    const SinCos c0 = rotate_quadrant(sincos_octant(qb0.th), qb0.q);
+                    const SinCos c1 = rotate_quadrant(sincos_octant(qb1.th), qb1.q);
+                    // Masks multiply (phases are finite): a select would let
+                    // the compiler move the phase arithmetic under a branch.
+                    const float m0 = (bx_ok && k <= klast) ? 1.f : 0.f;
+                    const float m1 = (bx_ok && k + 1 <= klast) ? 1.f : 0.f;
+                    e0 = make_float2(c0.c * m0, c0.s * m0);
+                    e1 = make_float2(c1.c * m1, c1.s * m1);
+                } else if (piece == 4) {          // store B(s+1); conj(Ey) of step s+2: reduction; fy(s+3)
+                    P::template store_b_words<BC>(sB0 + (cur ^ 1) * kBBytes8, bx, bk, P::split_b(e0), P::split_b(e1));
+                    qe = reduce_quarter_turns(tfy * kQuarterTurnsPerRad * yr);
+                    load_fy(s + 3);
+                } else {                          // conj(Ey) of step s+2
+                    const SinCos c = rotate_quadrant(sincos_octant(qe.th), qe.q);
+                    const float m = (ey_ok && (s + 2) * KC + ek <= klast) ? 1.f : 0.f;
+                    sE[cur][ey][ecol] = make_float2(c.c * m, c.s * m);
+                }
+            };
+            P::template mma_with<NT, BC, true>(sA0 + cur * P::kABytes, sB0 + cur * kBBytes8, wm * (nt * 32),
+                                               wn * 32, lane, acc_re, acc_im, prod);
+            __syncthreads();
+        }
+        for (; s < nsteps; ++s) {
+            const int cur = s & 1;
+            P::template mma<NT, BC>(sA0 + cur * P::kABytes, sB0 + cur * kBBytes8, wm * (nt * 32), wn * 32, lane,
+                                    nvalid, acc_re, acc_im);
+            if (s + 1 < nsteps) {
+                gen_a(cur ^ 1, cur ^ 1);              // W(s+1) from d(s+1) and E(s+1)
+                if (s + 2 < nsteps) load_d(s + 2);
+                gen_b(cur ^ 1, s + 1);                // uses fx(s+1)
+                if (s + 2 < nsteps) gen_e(cur, s + 2);   // uses fy(s+2)
+                load_fx(s + 2);
+                load_fy(s + 3);
+            }
+            __syncthreads();
+        }
+        // Coil combine of this group, then the two row-waves of each x
+        // quarter meet through LDS and the group's partial image is written.
+        float2 part[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) part[i] = make_float2(0.f, 0.f);
+        if (xe < nx) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                if (t < nvalid) {
+                    const int g = g0 + wm * nt + t;
+                    const float2* sg = sm + (int64_t)g * npix;
+                    constexpr float kInvB = 1.0f / P::kBScale;
+                    float us = 1.0f;
+                    if constexpr (P::kScaled) us = sUnscale[wm * nt + t];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int y = y0 + (i >> 2) * 8 + h * 4 + (i & 3);
+                        if (y < ny)
+                            part[i] = cadd(part[i], cmulc(sg[(int64_t)y * nx + xe],
+                                                          make_float2(acc_re[t][i] * kInvB * us,
+                                                                      acc_im[t][i] * kInvB * us)));
+                    }
+                }
+            }
+        }
+        float2* red = reinterpret_cast<float2*>(smem);   // 4 (wn) x 16 x 64 complex
+        if (wm == 1) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) red[(wn * 16 + i) * 64 + lane] = part[i];
+        }
+        __syncthreads();
+        if (wm == 0 && xe < nx) {
+            const int plane = sp * ncgroups + gi;
+            float2* out = it.part + ((int64_t)plane * it.nb + b) * npix;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int y = y0 + (i >> 2) * 8 + h * 4 + (i & 3);
+                if (y < ny) out[(int64_t)y * nx + xe] = cadd(part[i], red[(wn * 16 + i) * 64 + lane]);
+            }
+        }
+    }
+}
+
 }  // namespace
 
 int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb) {
@@ -927,8 +1329,9 @@ namespace {
 
 // Launch one kernel variant per row-tile class: items are grouped by their NT
 // (each class keeps its own contiguous tile numbering).
-template <class Pick, class Launch>
-hipError_t launch_by_nt(const NudftTable& t, Pick nt_of, Launch launch) {
+// tiles_of gives an item's tile count for the kernel being launched.
+template <class Pick, class Tiles, class Launch>
+hipError_t launch_by_nt(const NudftTable& t, Pick nt_of, Tiles tiles_of, Launch launch) {
     for (int nt = 2; nt <= kNT; ++nt) {
         NudftTable sub;
         sub.nitems = 0;
@@ -938,7 +1341,8 @@ hipError_t launch_by_nt(const NudftTable& t, Pick nt_of, Launch launch) {
             if (nt_of(t.it[i]) != nt) continue;
             sub.it[sub.nitems] = t.it[i];
             sub.it[sub.nitems].tile_begin = sub.total_tiles;
-            sub.total_tiles += t.it[i].ntiles;
+            sub.it[sub.nitems].ntiles = (int32_t)tiles_of(t.it[i]);
+            sub.total_tiles += sub.it[sub.nitems].ntiles;
             ++sub.nitems;
         }
         if (sub.total_tiles == 0) continue;
@@ -966,11 +1370,26 @@ hipError_t adj_variant(const NudftTable& t, int nt, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <class P>
+hipError_t adj8_variant(const NudftTable& t, int nt, hipStream_t s) {
+    const dim3 g(t.total_tiles), b(kThreads8);
+    if (nt == 2) hipLaunchKernelGGL((nudft_adj8<P, 2>), g, b, 0, s, t);
+    else if (nt == 3) hipLaunchKernelGGL((nudft_adj8<P, 3>), g, b, 0, s, t);
+    else hipLaunchKernelGGL((nudft_adj8<P, 4>), g, b, 0, s, t);
+    return hipGetLastError();
+}
+
+// Tiles of the split-form adjoint: (slice, 32 y, 128 x, sample split).
+int64_t adj8_tiles(const NudftItem& it) {
+    return (int64_t)it.nb * ceil_div(it.nx, kAdjCols8) * ceil_div(it.ny, kAdjRows) * it.ksplit;
+}
+
 }  // namespace
 
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s) {
     if (t.total_tiles <= 0) return hipSuccess;
     return launch_by_nt(t, [](const NudftItem& it) { return fwd_nt(it.ny); },
+                        [](const NudftItem& it) { return (int64_t)it.ntiles; },
                         [&](const NudftTable& sub, int nt) {
                             return precision == MRI_BF16X3   ? fwd_variant<PolBF16>(sub, nt, s)
                                    : precision == MRI_FP16X3 ? fwd_variant<PolF16>(sub, nt, s)
@@ -987,11 +1406,14 @@ hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t 
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); },
+    if (precision == MRI_FP32)
+        return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); },
+                            [](const NudftItem& it) { return (int64_t)it.ntiles; },
+                            [&](const NudftTable& sub, int nt) { return adj_variant<PolF32>(sub, nt, s); });
+    return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); }, adj8_tiles,
                         [&](const NudftTable& sub, int nt) {
-                            return precision == MRI_BF16X3   ? adj_variant<PolBF16>(sub, nt, s)
-                                   : precision == MRI_FP16X3 ? adj_variant<PolF16>(sub, nt, s)
-                                                             : adj_variant<PolF32>(sub, nt, s);
+                            return precision == MRI_BF16X3 ? adj8_variant<PolBF16>(sub, nt, s)
+                                                           : adj8_variant<PolF16>(sub, nt, s);
                         });
 }
 

@@ -18,12 +18,19 @@ struct SinCos {
     float s, c;
 };
 
-// sin and cos of 2 pi * t4 / 4 (t4 = 4 f r, in quarter turns), FP64 reduction.
-__device__ __forceinline__ SinCos sincos_quarter_turns(double t4) {
+// The evaluation in three steps (so a kernel can spread them between other
+// work): reduction, the two polynomials, the quadrant rotation.
+struct QuarterTurn {
+    float th;    // reduced angle in radians, [-pi/4, pi/4]
+    int q;       // quadrant, 0..3
+};
+__device__ __forceinline__ QuarterTurn reduce_quarter_turns(double t4) {
     const double n = rint(t4);
     const float v = static_cast<float>(t4 - n);           // [-0.5, 0.5] quarter turns
-    const int q = static_cast<int>(n) & 3;
-    const float th = v * 1.57079632679489661923f;          // [-pi/4, pi/4]
+    return {v * 1.57079632679489661923f, static_cast<int>(n) & 3};
+}
+// sin and cos of th on [-pi/4, pi/4].
+__device__ __forceinline__ SinCos sincos_octant(float th) {
     const float t2 = th * th;
     // sin th = th (1 - t2/3! + t2^2/5! - t2^3/7! + t2^4/9!)
     float ps = fmaf(t2, 2.7557319224e-6f, -1.9841269841e-4f);
@@ -35,14 +42,23 @@ __device__ __forceinline__ SinCos sincos_quarter_turns(double t4) {
     pc = fmaf(t2, pc, 4.1666666667e-2f);
     pc = fmaf(t2, pc, -0.5f);
     const float cs = fmaf(t2, pc, 1.0f);
-    // rotate by q quarter turns: (s, c) -> q=1: (c, -s), q=2: (-s, -c), q=3: (-c, s)
+    return {sn, cs};
+}
+// Rotate by q quarter turns: (s, c) -> q=1: (c, -s), q=2: (-s, -c), q=3: (-c, s).
+__device__ __forceinline__ SinCos rotate_quadrant(SinCos sc, int q) {
     SinCos r;
     const bool swap = q & 1;
-    const float a = swap ? cs : sn;
-    const float b = swap ? sn : cs;
+    const float a = swap ? sc.c : sc.s;
+    const float b = swap ? sc.s : sc.c;
     r.s = (q & 2) ? -a : a;
     r.c = ((q + 1) & 2) ? -b : b;
     return r;
+}
+
+// sin and cos of 2 pi * t4 / 4 (t4 = 4 f r, in quarter turns), FP64 reduction.
+__device__ __forceinline__ SinCos sincos_quarter_turns(double t4) {
+    const QuarterTurn r = reduce_quarter_turns(t4);
+    return rotate_quadrant(sincos_octant(r.th), r.q);
 }
 
 // exp(-2 pi i f r) with f4 = 4 f precomputed per sample.
