@@ -28,7 +28,7 @@ def _unmangle(name: str) -> str:
     """Readable names for the templated NUDFT kernels that the profiler leaves
     mangled (their template arguments include 16-bit float types)."""
     import re
-    m = re.match(r"_ZN3mri12_GLOBAL__N_1\d+(nudft_(?:fwd|adj))INS0_\d+(\w+?)E+(?:Li(\d)E)?", name)
+    m = re.match(r"_ZN3mri12_GLOBAL__N_1\d+(nudft_(?:fwd|adj8?))INS0_\d+(\w+?)E+(?:Li(\d)E)?", name)
     if m:
         nt = f", {m.group(3)}" if m.group(3) else ""
         return f"{m.group(1)}<{_POLICIES.get(m.group(2), m.group(2))}{nt}>(mri::NudftTable)"
