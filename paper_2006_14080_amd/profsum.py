@@ -5,11 +5,15 @@
     python -m paper_2006_14080_amd.profsum traffic <fetch.csv> <write.csv> --cmd "<command>" [--json out.json --key fp32]
     python -m paper_2006_14080_amd.profsum vecbw <run_kernel_stats.csv> --cmd "<command>" --npix N --coils C --planes P
     python -m paper_2006_14080_amd.profsum busy <run_kernel_trace.csv> --cmd "<command>"
+    python -m paper_2006_14080_amd.profsum grid <run_kernel_trace.csv> --cmd "<command>"
 
 ``vecbw`` turns the durations of the solver's memory-bound kernels into
 achieved bandwidth from their algorithmic bytes per pixel (listed in
 VEC_BYTES; N = pixels of all slices, C = coils, P = adjoint partial images
 per slice), against the 8 TB/s HBM peak.
+
+``grid`` lists the NUDFT kernels of a run per (kernel, grid size), so runs
+that launch one kernel at several shapes keep them apart.
 
 ``stats`` lists per-kernel call counts and durations; ``pmc`` averages every
 counter per kernel over its dispatches (FETCH_SIZE / WRITE_SIZE are KiB per
@@ -211,9 +215,23 @@ def busy(trace_csv, top):
     return out
 
 
+def grid(trace_csv):
+    """Calls and average duration per (NUDFT kernel, grid size)."""
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        k = short(r["Kernel_Name"])
+        if not k.startswith("nudft"):
+            continue
+        agg[(k, int(r.get("Grid_Size") or r["Grid_Size_X"]))].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = [f"{'kernel':44s} {'grid (threads)':>15s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s}"]
+    for (k, g), d in sorted(agg.items(), key=lambda x: (x[0][0], -x[0][1])):
+        out.append(f"{k:44s} {g:15d} {len(d):6d} {sum(d) / len(d):10.2f} {min(d):10.2f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "pmc", "traffic", "vecbw", "busy"])
+    ap.add_argument("mode", choices=["stats", "pmc", "traffic", "vecbw", "busy", "grid"])
     ap.add_argument("csv")
     ap.add_argument("csv2", nargs="?")
     ap.add_argument("--cmd", required=True)
@@ -251,6 +269,12 @@ def main():
                 json.dump(d, fh, indent=1, sort_keys=True)
         for k, v in t.items():
             print(k, v)
+        return 0
+    if a.mode == "grid":
+        print("# NUDFT kernels per launch shape from a rocprofv3 kernel trace")
+        print(f"# command: {a.cmd}")
+        for line in grid(a.csv):
+            print(line)
         return 0
     print(f"# rocprofv3 summary ({a.mode})")
     print(f"# command: {a.cmd}")
