@@ -62,7 +62,6 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
 // LDS planes with K contiguous: A (Ar, Ai); B (Br, Bi, -Bi).  Lanes 0-31 read
 // plane Ar / Br / Bi, lanes 32-63 read Ai / -Bi / Br, four K values per read.
 struct PolF32 {
-    static constexpr bool kPrioritiseMfma = false;   // measured: no gain (MFMA-bound already)
     static constexpr bool kInterleave = false;       // FP32 MFMA and VALU do not execute at once (counters)
     static constexpr bool kPresplitA = false;        // forward A staged from the FP32 coil-weighted image
     static constexpr bool kScaled = false;
@@ -146,7 +145,6 @@ struct PolSplit {
     typedef T vec2 __attribute__((ext_vector_type(2)));
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    static constexpr bool kPrioritiseMfma = true;    // measured: +5% on the VALU-heavy forward
     static constexpr bool kInterleave = true;        // producers run between the MFMAs (mma_with)
     static constexpr bool kPresplitA = true;         // forward A pre-split into operand chunks once per call
     static constexpr bool kScaled = Scaled;
@@ -689,10 +687,8 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
                         P::template store_b_words<64>(sB0 + (cur ^ 1) * P::kBBytes, pc, pj, r0, r1);
                     }
                 };
-                if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);
                 P::template mma_with<NT, 64, false>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32),
                                                     wn * 32, lane, acc_re, acc_im, prod);
-                if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
                 wait_a();
                 __syncthreads();
             }
@@ -933,10 +929,8 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
         __syncthreads();
         for (int s = 0; s < nsteps; ++s) {
             const int cur = s & 1;
-            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(1);   // MFMA burst ahead of the co-resident wave's VALU
             P::template mma<NT>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32), wn * 32, lane, nvalid,
                    acc_re, acc_im);
-            if constexpr (P::kPrioritiseMfma) __builtin_amdgcn_s_setprio(0);
             if (s + 1 < nsteps) {
                 gen_a(cur ^ 1, cur ^ 1);              // W(s+1) from d(s+1) and E(s+1)
                 if (s + 2 < nsteps) load_d(s + 2);
