@@ -113,12 +113,36 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
  * No density compensation.  The sample sum is split over workgroups and the
  * partial images are added in a fixed order, so results are bitwise
  * reproducible run to run.
- *   y [B][nc][nk], x [B][ny][nx] (written).  Workspace: MRI_OP_ADJOINT.
+ *   y [B][nc][nk], x [B][ny][nx] (written).  Workspace: MRI_OP_ADJOINT; it
+ *   holds the partial images and the phase tables exp(+i w_k x), exp(+i w_k y)
+ *   of the trajectory, (nx + ny) * nk * 8 bytes per trajectory (Alg. 1 forms
+ *   the same factors), rebuilt by every call.  Equivalent to
+ *   nudft_adjoint_prepare followed by nudft_adjoint_prepared.
  * Errors: as nudft_forward.
  */
 int nudft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps,
                   const double* traj, mri_c32* x, int precision,
                   void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * nudft_adjoint_prepare -- fill the phase tables of nudft_adjoint for one
+ * shape and trajectory into an MRI_OP_ADJOINT workspace (the values are those
+ * of Alg. 1's phase factors, with the FP64 argument reduction).
+ * nudft_adjoint_prepared -- nudft_adjoint using the tables already in ws,
+ * for callers that apply the adjoint repeatedly with a fixed trajectory (as
+ * admm_solve does inside): results are bit-identical to nudft_adjoint.  The
+ * tables must come from nudft_adjoint_prepare (or nudft_adjoint) with the
+ * same shape, trajectory contents and workspace, and be complete on the
+ * stream (same stream, or synchronised); otherwise the result is undefined.
+ * Only the partial-image part of ws is written, so prepared calls may follow
+ * each other on one stream.
+ * Errors: as nudft_forward (nudft_adjoint_prepare reads only shape, traj, ws).
+ */
+int nudft_adjoint_prepare(const mri_shape* shape, const double* traj,
+                          void* ws, size_t ws_bytes, void* stream);
+int nudft_adjoint_prepared(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps,
+                           const double* traj, mri_c32* x, int precision,
+                           void* ws, size_t ws_bytes, void* stream);
 
 /*
  * tv_forward -- g = Theta(x), the finite-difference sparsifying transform

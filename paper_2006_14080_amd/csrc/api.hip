@@ -104,8 +104,20 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
     return MRI_OK;
 }
 
-int nudft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps, const double* traj,
-                  mri_c32* x, int precision, void* ws, size_t ws_bytes, void* stream) {
+int nudft_adjoint_prepare(const mri_shape* shape, const double* traj, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if (!traj) return MRI_EINVAL;
+    if (!ws || ws_bytes < adjoint_ws(*shape)) return MRI_ENOMEM;
+    NudftItem it = base_item(*shape, nullptr, traj);
+    bind_adj_tables(it, *shape, ws);
+    const NudftTable t = single_table(it, 1);
+    MRI_HIP(launch_adj_phases(t, static_cast<hipStream_t>(stream)));
+    return MRI_OK;
+}
+
+int nudft_adjoint_prepared(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps, const double* traj,
+                           mri_c32* x, int precision, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_shape(shape);
     if (rc) return rc;
     if ((rc = check_precision(precision))) return rc;
@@ -116,6 +128,7 @@ int nudft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps
     it.data = const_cast<float2*>(reinterpret_cast<const float2*>(y));
     it.part = static_cast<float2*>(ws);
     adj_split(shape->nx, shape->ny, shape->ncoils, shape->nk, shape->batch, precision, &it.ksplit, &it.kper);
+    bind_adj_tables(it, *shape, ws);
     const NudftTable t = single_table(it, adj_tiles_per_split(shape->nx, shape->ny, shape->batch) * it.ksplit);
     hipStream_t s = static_cast<hipStream_t>(stream);
     MRI_HIP(launch_nudft_adjoint(t, precision, s));
@@ -123,6 +136,16 @@ int nudft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps
                                 (int64_t)shape->nx * shape->ny * shape->batch,
                                 reinterpret_cast<float2*>(x), s));
     return MRI_OK;
+}
+
+int nudft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps, const double* traj,
+                  mri_c32* x, int precision, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if ((rc = check_precision(precision))) return rc;
+    if (!x || !smaps || !traj || !y) return MRI_EINVAL;
+    if ((rc = nudft_adjoint_prepare(shape, traj, ws, ws_bytes, stream))) return rc;
+    return nudft_adjoint_prepared(shape, y, smaps, traj, x, precision, ws, ws_bytes, stream);
 }
 
 int tv_forward(const mri_shape* shape, const mri_c32* x, mri_c32* g, void* stream) {

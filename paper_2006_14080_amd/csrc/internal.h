@@ -32,6 +32,11 @@ struct NudftItem {
     int32_t active_stride;
     int32_t ksplit;                          // adjoint: sample-range splits
     int32_t kper;                            // adjoint: samples per split (multiple of 8)
+    // Adjoint phase tables (k_adj_phases, once per trajectory): exp(+i w_x,k x)
+    // [nk][nx] and exp(+i w_y,k y) [nk][ny] (centred offsets), per slice when
+    // the trajectory is per slice (stride 0 = shared).
+    float2* ephx;  int64_t ephx_bs;
+    float2* ephy;  int64_t ephy_bs;
     int32_t tile_begin;                      // first tile of this item
     int32_t ntiles;
     int64_t cw_begin;                        // first coil-weighting element of this item
@@ -43,6 +48,7 @@ struct NudftTable {
     int64_t cw_total;                        // coil-weighting elements over all items
     NudftItem it[kMaxItems];
 };
+static_assert(sizeof(NudftTable) <= 4096, "a NudftTable is passed as a kernel argument");
 
 // Forward tiling: 64 samples per workgroup, rows = all y in chunks of 256.
 constexpr int kFwdCols = 64;
@@ -102,6 +108,10 @@ __host__ __device__ inline int64_t adj_partial_elems(int nx, int ny, int nc, int
 __host__ __device__ inline int32_t* adj_scale_exp(float2* part, int nx, int ny, int nc, int nb, int ksplit) {
     return reinterpret_cast<int32_t*>(part + adj_partial_elems(nx, ny, nc, nb, ksplit));
 }
+// Complex elements of the adjoint's phase tables (nbt trajectories).
+__host__ __device__ inline int64_t adj_table_elems(int nx, int ny, int64_t nk, int nbt) {
+    return (int64_t)nbt * nk * ((int64_t)nx + ny);
+}
 // Choose the sample-range split of the adjoint for one problem.
 void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
                int32_t* ksplit, int32_t* kper);
@@ -111,5 +121,7 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
 hipError_t launch_coil_weight(const NudftTable& t, int precision, hipStream_t s);
 hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t s);
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s);
+// Fill the adjoint phase tables of every item of t (ephx, ephy).
+hipError_t launch_adj_phases(const NudftTable& t, hipStream_t s);
 
 }  // namespace mri

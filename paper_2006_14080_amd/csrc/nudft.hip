@@ -524,6 +524,38 @@ __global__ __launch_bounds__(256) void k_adj_scale(const NudftTable tab) {
     }
 }
 
+// Adjoint phase tables: exp(+i 2 pi f r) for every sample and every centred x
+// (then y) offset, with the reduction of phase.h, i.e. the values the adjoint
+// would otherwise form per step; one thread per table element.  Filled once
+// per trajectory (once per solve).
+__global__ __launch_bounds__(256) void k_adj_phases(const NudftTable tab) {
+    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int k = 0;
+    for (; k < tab.nitems; ++k) {
+        const NudftItem& c = tab.it[k];
+        const int64_t n = adj_table_elems(c.nx, c.ny, c.nk, c.traj_bs ? c.nb : 1);
+        if (g < n) break;
+        g -= n;
+    }
+    if (k >= tab.nitems) return;
+    const NudftItem& it = tab.it[k];
+    const int64_t nx = it.nx, ny = it.ny;
+    const int64_t per = it.nk * (nx + ny);                // elements per trajectory
+    const int64_t bt = g / per;
+    int64_t r = g - bt * per;
+    const double* traj = it.traj + bt * it.traj_bs;
+    if (r < it.nk * nx) {
+        const int64_t kk = r / nx;
+        const int x = (int)(r - kk * nx);
+        it.ephx[bt * it.ephx_bs + r] = phase_pos(traj[2 * kk] * kQuarterTurnsPerRad, (double)(x - it.nx / 2));
+    } else {
+        r -= it.nk * nx;
+        const int64_t kk = r / ny;
+        const int y = (int)(r - kk * ny);
+        it.ephy[bt * it.ephy_bs + r] = phase_pos(traj[2 * kk + 1] * kQuarterTurnsPerRad, (double)(y - it.ny / 2));
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Forward: tile = (slice, coil, 64 samples); rows = every y in passes of 256.
 // In the split forms the next B stage is produced between the MFMA groups of
@@ -799,15 +831,15 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
     const int x0 = xb * kAdjCols, y0 = yb * kAdjRows;
     const int64_t npix = (int64_t)nx * ny;
-    const double* traj = it.traj + b * it.traj_bs;
     const float2* sm = it.smaps + b * it.smaps_bs;
     const float2* dat = it.data + (int64_t)b * nc * nk;
-    const int xh = nx / 2, yh = ny / 2;
     const int64_t kbeg = (int64_t)sp * it.kper;
     const int64_t kend = min(nk, kbeg + it.kper);
     const int nsteps = (int)ceil_div(kend - kbeg, KC);
     const int klast = (int)(kend - kbeg - 1);             // last sample of the split, relative
-    const double* trs = traj + 2 * kbeg;
+    // Phase rows of the split's samples (tables filled by k_adj_phases).
+    const float2* phx = it.ephx + b * it.ephx_bs + kbeg * nx;
+    const float2* phy = it.ephy + b * it.ephy_bs + kbeg * ny;
     const int32_t* aexp = nullptr;
     if constexpr (P::kScaled) aexp = adj_scale_exp(it.part, nx, ny, nc, it.nb, it.ksplit);
 
@@ -815,10 +847,10 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     const int ey = tid & 31, ek = tid >> 5;              // E: (y, k)
     const int bx = tid & 63, bk = (tid >> 6) * 2;        // B: (x, k pair)
     const int ac = tid >> 5, ay = tid & 31;              // A: (coil, y)
-    const double yr = (double)(y0 + ey - yh);
     const bool ey_ok = y0 + ey < ny;
-    const double xr = (double)(x0 + bx - xh);
     const bool bx_ok = x0 + bx < nx;
+    const int yc = ey_ok ? y0 + ey : ny - 1;             // in-bounds table columns
+    const int xc = bx_ok ? x0 + bx : nx - 1;
     const int xe = x0 + wn * 32 + l32;                   // epilogue column
 
     // Coils run in groups of 2 * NT, split between the two row-waves (NT coils
@@ -860,31 +892,26 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
                 for (int j = 0; j < KC; ++j) dreg[j] = drow[min(s * KC + j, klast)];
             }
         };
-        // Trajectory values are prefetched one step ahead of their use:
-        // tfx0/tfx1 for the next B stage, tfy for the E tile after that.
-        double tfx0, tfx1, tfy;
+        // Phases are prefetched one step ahead of their use: fx0/fx1 for the
+        // next B stage, fy for the E tile after that (rows clamped to the
+        // split's last sample; those samples are masked when staged).
+        float2 fx0, fx1, fy;
         auto load_fx = [&](int s) {
             const int k = s * KC + bk;
-            if (s * KC + KC - 1 <= klast) {
-                const double* q = trs + 2 * k;       // (x, y) of k, then of k + 1
-                tfx0 = q[0];
-                tfx1 = q[2];
-            } else {
-                tfx0 = trs[2 * min(k, klast)];
-                tfx1 = trs[2 * min(k + 1, klast)];
-            }
+            fx0 = phx[(int64_t)min(k, klast) * nx + xc];
+            fx1 = phx[(int64_t)min(k + 1, klast) * nx + xc];
         };
         auto load_fy = [&](int s) {
-            tfy = trs[2 * min(s * KC + ek, klast) + 1];
+            fy = phy[(int64_t)min(s * KC + ek, klast) * ny + yc];
         };
         auto gen_e = [&](int st, int s) {
-            float2 e = phase_pos(tfy * kQuarterTurnsPerRad, yr);
+            float2 e = fy;
             if (!(ey_ok && s * KC + ek <= klast)) e = make_float2(0.f, 0.f);
             sE[st][ey][ek] = e;
         };
         auto gen_b = [&](int st, int s) {
             const int k = s * KC + bk;
-            float2 e0 = phase_pos(tfx0 * kQuarterTurnsPerRad, xr), e1 = phase_pos(tfx1 * kQuarterTurnsPerRad, xr);
+            float2 e0 = fx0, e1 = fx1;
             if (!(bx_ok && k <= klast)) e0 = make_float2(0.f, 0.f);
             if (!(bx_ok && k + 1 <= klast)) e1 = make_float2(0.f, 0.f);
             P::store_b(sB0 + st * P::kBBytes, bx, bk, e0, e1);
@@ -1028,15 +1055,15 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
     const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
     const int x0 = xb * BC, y0 = yb * kAdjRows;
     const int64_t npix = (int64_t)nx * ny;
-    const double* traj = it.traj + b * it.traj_bs;
     const float2* sm = it.smaps + b * it.smaps_bs;
     const float2* dat = it.data + (int64_t)b * nc * nk;
-    const int xh = nx / 2, yh = ny / 2;
     const int64_t kbeg = (int64_t)sp * it.kper;
     const int64_t kend = min(nk, kbeg + it.kper);
     const int nsteps = (int)ceil_div(kend - kbeg, KC);
     const int klast = (int)(kend - kbeg - 1);             // last sample of the split, relative
-    const double* trs = traj + 2 * kbeg;
+    // Phase rows of the split's samples (tables filled by k_adj_phases).
+    const float2* phx = it.ephx + b * it.ephx_bs + kbeg * nx;
+    const float2* phy = it.ephy + b * it.ephy_bs + kbeg * ny;
     const int32_t* aexp = nullptr;
     if constexpr (P::kScaled) aexp = adj_scale_exp(it.part, nx, ny, nc, it.nb, it.ksplit);
 
@@ -1046,10 +1073,10 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
     const int bx = tid & 127, bk = (tid >> 7) * 2;       // B: (x, k pair)
     const int arow = tid & 255, ahalf = tid >> 8;        // A: row (coil, y), K half
     const int ac = arow >> 5, ay = arow & 31;
-    const double yr = (double)(y0 + ey - yh);
     const bool ey_ok = y0 + ey < ny;
-    const double xr = (double)(x0 + bx - xh);
     const bool bx_ok = x0 + bx < nx;
+    const int yc = ey_ok ? y0 + ey : ny - 1;             // in-bounds table columns
+    const int xc = bx_ok ? x0 + bx : nx - 1;
     const int xe = x0 + wn * 32 + l32;                   // epilogue column
 
     constexpr int nt = NT;
@@ -1083,27 +1110,27 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
                 for (int j = 0; j < 4; ++j) dreg[j] = drow[min(s * KC + 4 * ahalf + j, klast)];
             }
         };
-        double tfx0, tfx1, tfy;
+        // Phases prefetched one step ahead (rows clamped to the split's last
+        // sample; those samples are masked when staged).  Masks multiply (the
+        // phases are finite), which keeps the loops free of branches.
+        float2 fx0, fx1, fy;
         auto load_fx = [&](int s) {
             const int k = s * KC + bk;
-            tfx0 = trs[2 * min(k, klast)];
-            tfx1 = trs[2 * min(k + 1, klast)];
+            fx0 = phx[(int64_t)min(k, klast) * nx + xc];
+            fx1 = phx[(int64_t)min(k + 1, klast) * nx + xc];
         };
-        auto load_fy = [&](int s) { tfy = trs[2 * min(s * KC + ek, klast) + 1]; };
+        auto load_fy = [&](int s) { fy = phy[(int64_t)min(s * KC + ek, klast) * ny + yc]; };
         auto gen_e = [&](int st, int s) {
-            const SinCos c = sincos_quarter_turns(tfy * kQuarterTurnsPerRad * yr);
             const float m = (ey_ok && s * KC + ek <= klast) ? 1.f : 0.f;
-            sE[st][ey][ecol] = make_float2(c.c * m, c.s * m);
+            sE[st][ey][ecol] = make_float2(fy.x * m, fy.y * m);
         };
         auto gen_b = [&](int st, int s) {
             const int k = s * KC + bk;
-            const SinCos c0 = sincos_quarter_turns(tfx0 * kQuarterTurnsPerRad * xr);
-            const SinCos c1 = sincos_quarter_turns(tfx1 * kQuarterTurnsPerRad * xr);
             const float m0 = (bx_ok && k <= klast) ? 1.f : 0.f;
             const float m1 = (bx_ok && k + 1 <= klast) ? 1.f : 0.f;
             P::template store_b_words<BC>(sB0 + st * kBBytes8, bx, bk,
-                                          P::split_b(make_float2(c0.c * m0, c0.s * m0)),
-                                          P::split_b(make_float2(c1.c * m1, c1.s * m1)));
+                                          P::split_b(make_float2(fx0.x * m0, fx0.y * m0)),
+                                          P::split_b(make_float2(fx1.x * m1, fx1.y * m1)));
         };
         // W of this thread's row and K half: d conj(Ey) (with the coil's scale).
         auto gen_a = [&](int st, int est) {
@@ -1149,8 +1176,7 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
             // Steady state: every look-ahead load is a whole step, no branch.
             const int cur = s & 1;
             float2 w[4];
-            QuarterTurn qb0, qb1, qe;
-            float2 e0, e1;
+            typename P::Words r0;
             auto prod = [&](int piece) {
                 if (piece == 0) {                 // W(s+1), first two values
 #pragma unroll
@@ -1168,30 +1194,22 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
                     const float2* q = drow + (s + 2) * KC + 4 * ahalf;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) dreg[j] = q[j];
-                } else if (piece == 2) {          // conj(Ex) of step s+1: reductions; fx(s+2)
-                    qb0 = reduce_quarter_turns(tfx0 * kQuarterTurnsPerRad * xr);
-                    qb1 = reduce_quarter_turns(tfx1 * kQuarterTurnsPerRad * xr);
-                    const double* q = trs + 2 * ((s + 2) * KC + bk);
-                    tfx0 = q[0];
-                    tfx1 = q[2];
-                } else if (piece == 3) {          // polynomials, quadrants, masks
+                } else if (piece == 2) {          // conj(Ex) of step s+1: first value
                     const int k = (s + 1) * KC + bk;
-                    const SinCos c0 = rotate_quadrant(sincos_octant(qb0.th), qb0.q);
-                    const SinCos c1 = rotate_quadrant(sincos_octant(qb1.th), qb1.q);
-                    // Masks multiply (phases are finite): a select would let
-                    // the compiler move the phase arithmetic under a branch.
                     const float m0 = (bx_ok && k <= klast) ? 1.f : 0.f;
+                    r0 = P::split_b(make_float2(fx0.x * m0, fx0.y * m0));
+                } else if (piece == 3) {          // second value; store B(s+1); next phases
+                    const int k = (s + 1) * KC + bk;
                     const float m1 = (bx_ok && k + 1 <= klast) ? 1.f : 0.f;
-                    e0 = make_float2(c0.c * m0, c0.s * m0);
-                    e1 = make_float2(c1.c * m1, c1.s * m1);
-                } else if (piece == 4) {          // store B(s+1); conj(Ey) of step s+2: reduction; fy(s+3)
-                    P::template store_b_words<BC>(sB0 + (cur ^ 1) * kBBytes8, bx, bk, P::split_b(e0), P::split_b(e1));
-                    qe = reduce_quarter_turns(tfy * kQuarterTurnsPerRad * yr);
-                    load_fy(s + 3);
-                } else {                          // conj(Ey) of step s+2
-                    const SinCos c = rotate_quadrant(sincos_octant(qe.th), qe.q);
+                    P::template store_b_words<BC>(sB0 + (cur ^ 1) * kBBytes8, bx, bk, r0,
+                                                  P::split_b(make_float2(fx1.x * m1, fx1.y * m1)));
+                    const float2* q = phx + (int64_t)((s + 2) * KC + bk) * nx + xc;
+                    fx0 = q[0];
+                    fx1 = q[nx];
+                } else if (piece == 4) {          // conj(Ey) of step s+2; fy(s+3)
                     const float m = (ey_ok && (s + 2) * KC + ek <= klast) ? 1.f : 0.f;
-                    sE[cur][ey][ecol] = make_float2(c.c * m, c.s * m);
+                    sE[cur][ey][ecol] = make_float2(fy.x * m, fy.y * m);
+                    load_fy(s + 3);
                 }
             };
             P::template mma_with<NT, BC, true>(sA0 + cur * P::kABytes, sB0 + cur * kBBytes8, wm * (nt * 32),
@@ -1389,6 +1407,15 @@ hipError_t launch_nudft_forward(const NudftTable& t, int precision, hipStream_t 
                                    : precision == MRI_FP16X3 ? fwd_variant<PolF16>(sub, nt, s)
                                                              : fwd_variant<PolF32>(sub, nt, s);
                         });
+}
+
+hipError_t launch_adj_phases(const NudftTable& t, hipStream_t s) {
+    int64_t n = 0;
+    for (int i = 0; i < t.nitems; ++i)
+        n += adj_table_elems(t.it[i].nx, t.it[i].ny, t.it[i].nk, t.it[i].traj_bs ? t.it[i].nb : 1);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_phases, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, t);
+    return hipGetLastError();
 }
 
 hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t s) {

@@ -25,6 +25,8 @@ int check_params(const mri_admm_params* p);
 AdmmLayout admm_layout(const mri_shape& s, int precision);
 size_t forward_ws(const mri_shape& s);
 size_t adjoint_ws(const mri_shape& s);
+// Point an item's adjoint phase tables into its adjoint workspace (part).
+void bind_adj_tables(NudftItem& it, const mri_shape& s, void* part);
 
 // One problem of a plan: inputs and outputs (device pointers) and workspace.
 struct SolveBinding {

@@ -44,11 +44,25 @@ size_t forward_ws(const mri_shape& s) {
     return ws_align(f32 > bf ? f32 : bf);
 }
 
-size_t adjoint_ws(const mri_shape& s) {
+// Adjoint workspace: partial images and scale exponents, then the phase
+// tables (one per trajectory).
+size_t adjoint_tables_offset(const mri_shape& s) {
     int32_t ks, kp;
     adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, MRI_FP32, &ks, &kp);
     return ws_align(sizeof(float2) * (size_t)adj_partial_elems(s.nx, s.ny, s.ncoils, s.batch, ks) +
                     sizeof(int32_t) * (size_t)s.batch * s.ncoils * ks);
+}
+
+size_t adjoint_ws(const mri_shape& s) {
+    const int nbt = s.traj_batched ? s.batch : 1;
+    return adjoint_tables_offset(s) + ws_align(sizeof(float2) * (size_t)adj_table_elems(s.nx, s.ny, s.nk, nbt));
+}
+
+void bind_adj_tables(NudftItem& it, const mri_shape& s, void* part) {
+    it.ephx = reinterpret_cast<float2*>(static_cast<char*>(part) + adjoint_tables_offset(s));
+    it.ephx_bs = s.traj_batched ? s.nk * s.nx : 0;
+    it.ephy = it.ephx + (s.traj_batched ? s.batch : 1) * s.nk * s.nx;
+    it.ephy_bs = s.traj_batched ? s.nk * s.ny : 0;
 }
 
 AdmmLayout admm_layout(const mri_shape& s, int precision) {
@@ -165,6 +179,7 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         base.part = si.part;
         base.ksplit = L.ksplit;
         base.kper = L.kper;
+        bind_adj_tables(base, sh, at<char>(ws, L.part));
         base.active_stride = (int32_t)(sizeof(SolveScalars) / sizeof(int32_t));
         const int64_t ft = fwd_tiles(sh.nx, sh.ny, sh.ncoils, sh.nk, sh.batch);
         const int64_t at_ = adj_tiles_per_split(sh.nx, sh.ny, sh.batch) * L.ksplit;
@@ -206,6 +221,7 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
     } while (0)
 
 hipError_t enqueue_init(const Plan& p, hipStream_t s) {
+    PLAN_TRY(launch_adj_phases(p.afhd, s));     // the trajectory is fixed for the solve
     PLAN_TRY(launch_solve_init(p.st, s));
     PLAN_TRY(launch_nudft_adjoint(p.afhd, p.precision, s));
     PLAN_TRY(launch_adj_finish(p.st, kFinishFhd, s));

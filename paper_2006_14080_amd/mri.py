@@ -55,8 +55,9 @@ class MriAdmmStats(ctypes.Structure):
 
 STATS_BYTES = ctypes.sizeof(MriAdmmStats)
 
-EXPORTS = ["nudft_forward", "nudft_adjoint", "tv_forward", "tv_adjoint", "admm_solve",
-           "mri_workspace_bytes", "mri_strerror", "mri_last_hip_error"]
+EXPORTS = ["nudft_forward", "nudft_adjoint", "nudft_adjoint_prepare", "nudft_adjoint_prepared",
+           "tv_forward", "tv_adjoint", "admm_solve", "mri_workspace_bytes", "mri_strerror",
+           "mri_last_hip_error"]
 
 _lib = None
 
@@ -81,6 +82,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     prm = ctypes.POINTER(MriAdmmParams)
     lib.nudft_forward.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.nudft_adjoint.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.nudft_adjoint_prepare.argtypes = [shp, vp, vp, sz, vp]
+    lib.nudft_adjoint_prepared.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.tv_forward.argtypes = [shp, vp, vp, vp]
     lib.tv_adjoint.argtypes = [shp, vp, vp, vp]
     lib.admm_solve.argtypes = [shp, vp, vp, vp, vp, prm, vp, vp, vp, sz, vp]
@@ -90,7 +93,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mri_strerror.restype = ctypes.c_char_p
     lib.mri_last_hip_error.argtypes = []
     lib.mri_last_hip_error.restype = ctypes.c_char_p
-    for name in ["nudft_forward", "nudft_adjoint", "tv_forward", "tv_adjoint", "admm_solve"]:
+    for name in ["nudft_forward", "nudft_adjoint", "nudft_adjoint_prepare", "nudft_adjoint_prepared",
+                 "tv_forward", "tv_adjoint", "admm_solve"]:
         getattr(lib, name).restype = i32
     _lib = lib
     return lib
@@ -190,6 +194,35 @@ def nudft_adjoint(data: torch.Tensor, smaps: torch.Tensor, traj: torch.Tensor, n
     _check(lib.nudft_adjoint(ctypes.byref(sh), _ptr(data), _ptr(smaps), _ptr(traj), _ptr(out),
                              precision, _ptr(ws), n, _stream()), "nudft_adjoint")
     return out
+
+
+class AdjointPlan:
+    """F^H for a fixed trajectory: the phase tables are built once
+    (nudft_adjoint_prepare) into a workspace this object owns, and every call
+    applies nudft_adjoint_prepared (bit-identical to nudft_adjoint)."""
+
+    def __init__(self, smaps: torch.Tensor, traj: torch.Tensor, ny: int, nx: int, batch: int = 1,
+                 precision: int = FP32):
+        _need(smaps, torch.complex64, "smaps")
+        _need(traj, torch.float64, "traj")
+        self.smaps, self.traj, self.precision = smaps, traj, precision
+        self.shape = shape_of((batch, ny, nx), smaps, traj)
+        self.ws, self.ws_bytes = _workspace(self.shape, OP_ADJOINT, device=smaps.device)
+        _check(load().nudft_adjoint_prepare(ctypes.byref(self.shape), _ptr(traj), _ptr(self.ws),
+                                            self.ws_bytes, _stream()), "nudft_adjoint_prepare")
+
+    def __call__(self, data: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        sh = self.shape
+        _need(data, torch.complex64, "data")
+        if tuple(data.shape) != (sh.batch, sh.ncoils, sh.nk):
+            raise ValueError("data must be [B, nc, nk] of the plan's shape")
+        if out is None:
+            out = torch.empty((sh.batch, sh.ny, sh.nx), dtype=torch.complex64, device=data.device)
+        _need(out, torch.complex64, "out")
+        _check(load().nudft_adjoint_prepared(ctypes.byref(sh), _ptr(data), _ptr(self.smaps), _ptr(self.traj),
+                                             _ptr(out), self.precision, _ptr(self.ws), self.ws_bytes,
+                                             _stream()), "nudft_adjoint_prepared")
+        return out
 
 
 def tv_forward(image: torch.Tensor) -> torch.Tensor:

@@ -4,7 +4,8 @@
     python -m paper_2006_14080_amd.profile_driver vec SLICES
     python -m paper_2006_14080_amd.profile_driver shard PRECISION [repeats]
 
-The first form calls nudft_forward and nudft_adjoint at the 256x256 / 8-coil /
+The first form calls nudft_forward and the adjoint (nudft_adjoint_prepared,
+tables prepared once, as inside a solve) at the 256x256 / 8-coil /
 64x512-sample shape `repeats` times, then copies a 256 MiB buffer twice (a
 kernel of known traffic: reads 256 MiB, writes 256 MiB) so FETCH_SIZE /
 WRITE_SIZE can be calibrated in the same run.
@@ -88,8 +89,9 @@ def shard_timings(prec: int, repeats: int, parts: int = 8):
             nk = tr.shape[0]
             y = torch.empty((1, wl.nc, nk), dtype=torch.complex64, device="cuda")
             x = torch.empty((1, wl.ny, wl.nx), dtype=torch.complex64, device="cuda")
+            plan = mri.AdjointPlan(sm, gt, wl.ny, wl.nx, precision=prec)
             fwd = lambda: mri.nudft_forward(img, sm, gt, precision=prec, out=y)
-            adj = lambda: mri.nudft_adjoint(gd, sm, gt, wl.ny, wl.nx, precision=prec, out=x)
+            adj = lambda: plan(gd, out=x)
             fwd(), adj()
             tf, ta = _time_ms(fwd, repeats), _time_ms(adj, repeats)
             flop = 8.0 * nk * wl.nx * wl.ny * wl.nc
@@ -113,9 +115,10 @@ def main(argv):
     g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     img, sm, tr = g(p.truth), g(p.smaps), g(p.traj)
     dat = g(synth.random_complex((1, wl.nc, wl.nk), 1))
+    plan = mri.AdjointPlan(sm, tr, wl.ny, wl.nx, precision=prec)   # phase tables once, as in a solve
     for _ in range(n):
         mri.nudft_forward(img, sm, tr, precision=prec)
-        mri.nudft_adjoint(dat, sm, tr, wl.ny, wl.nx, precision=prec)
+        plan(dat)
     torch.cuda.synchronize()
     src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)

@@ -29,8 +29,8 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = _declared_functions()
-    for n in ["nudft_forward", "nudft_adjoint", "tv_forward", "tv_adjoint", "admm_solve",
-              "mri_workspace_bytes", "mri_strerror"]:
+    for n in ["nudft_forward", "nudft_adjoint", "nudft_adjoint_prepare", "nudft_adjoint_prepared",
+              "tv_forward", "tv_adjoint", "admm_solve", "mri_workspace_bytes", "mri_strerror"]:
         assert n in names
 
 
@@ -60,7 +60,11 @@ def test_workspace_sizes(lib):
     # element, as in FP32), FP16x3 with one float scale per row
     assert mri.workspace_bytes(sh, mri.OP_FORWARD) == 8 * 256 * 256 * 8 + 4 * 8 * 256
     adj = mri.workspace_bytes(sh, mri.OP_ADJOINT)
-    assert adj >= 256 * 256 * 8 and adj % 256 == 0
+    # partial images plus the phase tables exp(+i w x), exp(+i w y): (nx + ny) nk
+    assert adj >= 256 * 256 * 8 + (256 + 256) * 32768 * 8 and adj % 256 == 0
+    # per-slice trajectories: one table per slice
+    shb = mri.make_shape(256, 256, 8, 32768, batch=3, traj_batched=True)
+    assert mri.workspace_bytes(shb, mri.OP_ADJOINT) >= 3 * (256 + 256) * 32768 * 8
     total = mri.workspace_bytes(sh, mri.OP_ADMM, p)
     assert total > 12 * 256 * 256 * 8 + 8 * 32768 * 8
     bad = mri.make_shape(0, 256, 8, 32768)
@@ -99,3 +103,9 @@ def test_null_pointers_rejected(lib):
     assert lib.nudft_forward(ctypes.byref(sh), None, fake, fake, fake, 0, None, 0, None) == -1
     assert lib.tv_forward(ctypes.byref(sh), None, fake, None) == -1
     assert lib.nudft_adjoint(ctypes.byref(sh), fake, fake, fake, fake, 0, None, 0, None) == -2
+    n = mri.workspace_bytes(sh, mri.OP_ADJOINT)
+    assert lib.nudft_adjoint_prepare(ctypes.byref(sh), None, fake, n, None) == -1
+    assert lib.nudft_adjoint_prepare(ctypes.byref(sh), fake, fake, n - 1, None) == -2
+    assert lib.nudft_adjoint_prepared(ctypes.byref(sh), fake, fake, fake, None, 0, fake, n, None) == -1
+    assert lib.nudft_adjoint_prepared(ctypes.byref(sh), fake, fake, fake, fake, 0, None, 0, None) == -2
+    assert lib.nudft_adjoint_prepared(ctypes.byref(sh), fake, fake, fake, fake, 7, fake, n, None) == -1

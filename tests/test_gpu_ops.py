@@ -242,6 +242,26 @@ def test_full_batch_launch_sampled(prec):
         assert rel(got, onudft.adjoint_pixels(dat[b], sm, tr, rows, cols)) <= TOL
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("traj_batched", [False, True])
+def test_adjoint_plan_matches_single_calls(prec, traj_batched):
+    # Phase tables built once (nudft_adjoint_prepare) and reused by several
+    # prepared calls give the single-call results bit for bit, and stay
+    # within the per-operator bar of the oracle.
+    nx, ny, nc, nk, batch = 70, 46, 5, 900, 2
+    img, sm, tr, _ = _inputs(nx, ny, nc, nk, batch, 110, traj_batched=traj_batched)
+    gs, gt = _gpu(sm), _gpu(tr)
+    plan = mri.AdjointPlan(gs, gt, ny, nx, batch=batch, precision=prec)
+    for seed in (111, 112):
+        dat = synth.random_complex((batch, nc, nk), seed)
+        got = plan(_gpu(dat))
+        ref = mri.nudft_adjoint(_gpu(dat), gs, gt, ny, nx, precision=prec)
+        assert torch.equal(got, ref)
+        g = got.cpu().numpy()
+        for b in range(batch):
+            assert rel(g[b], onudft.adjoint(dat[b], sm, _per_slice(tr, b, traj_batched))) <= TOL
+
+
 @pytest.mark.parametrize("nx,ny,batch", [(32, 32, 1), (7, 5, 3), (1, 9, 2), (300, 2, 1)])
 def test_tv_parity(nx, ny, batch):
     x = synth.random_complex((batch, ny, nx), 80)
