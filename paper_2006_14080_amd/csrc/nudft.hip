@@ -814,16 +814,17 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
     const NudftItem& it = tab.it[find_item(tab, tile)];
     const int nx = it.nx, ny = it.ny, nc = it.nc;
     const int64_t nk = it.nk;
-    // Sample splits vary fastest: the splits of one pixel tile run as
-    // neighbours on one XCD and share its L2 for the coil maps they all read.
+    // Pixel tiles vary fastest (y blocks, then x blocks), then sample splits:
+    // the workgroups running together on one XCD work on the same split, so
+    // they read the same phase-table rows (and data) in step through its L2.
     int local = tile - it.tile_begin;
     const int nxb = (nx + kAdjCols - 1) / kAdjCols, nyb = (ny + kAdjRows - 1) / kAdjRows;
-    const int sp = local % it.ksplit;
-    local /= it.ksplit;
+    const int yb = local % nyb;
+    local /= nyb;
     const int xb = local % nxb;
     local /= nxb;
-    const int yb = local % nyb;
-    const int b = local / nyb;
+    const int sp = local % it.ksplit;
+    const int b = local / it.ksplit;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1040,14 +1041,14 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
     const NudftItem& it = tab.it[find_item(tab, tile)];
     const int nx = it.nx, ny = it.ny, nc = it.nc;
     const int64_t nk = it.nk;
-    int local = tile - it.tile_begin;
+    int local = tile - it.tile_begin;          // y blocks fastest, then x blocks, then splits
     const int nxb = (nx + BC - 1) / BC, nyb = (ny + kAdjRows - 1) / kAdjRows;
-    const int sp = local % it.ksplit;
-    local /= it.ksplit;
+    const int yb = local % nyb;
+    local /= nyb;
     const int xb = local % nxb;
     local /= nxb;
-    const int yb = local % nyb;
-    const int b = local / nyb;
+    const int sp = local % it.ksplit;
+    const int b = local / it.ksplit;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
 
     const int tid = threadIdx.x, lane = tid & 63;
