@@ -939,7 +939,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
             acc_im[t] = floatx16{0};
         }
         // Prologue: E(0), d(0) -> A(0), B(0); E(1), d(1) and the next
-        // trajectory values ready for the loop.
+        // phase values ready for the loop.
         load_fy(0);
         gen_e(0, 0);
         load_d(0);
@@ -1020,12 +1020,12 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
 // workgroup per CU).  The GEMM rows are (coil, y) as in nudft_adj; doubling
 // the x extent lets every W = d conj(Ey) value feed twice the MFMAs, which
 // cuts the vector work per matrix instruction by about a quarter.  Each
-// thread forms half a W row (4 K values), two conj(Ex) phases and one
-// conj(Ey) phase per step (waves 4-7 evaluate the same conj(Ey) phases as
-// waves 0-3 and store them into the tile's padding column, so every wave does
-// the same work and the loop has no role branch).  Steps whose look-ahead
-// loads are whole steps run with the producers interleaved between the MFMA
-// groups; the split's last steps take a plain loop.
+// thread forms half a W row (4 K values) and stages two conj(Ex) values and
+// one conj(Ey) value per step from the phase tables (waves 4-7 stage the same
+// conj(Ey) values as waves 0-3 into the tile's padding column, so every wave
+// does the same work and the loop has no role branch).  Steps whose
+// look-ahead loads are whole steps run with the producers interleaved between
+// the MFMA groups; the split's last steps take a plain loop.
 // ---------------------------------------------------------------------------
 template <class P, int NT>
 __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab) {
@@ -1156,7 +1156,7 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
             acc_im[t] = floatx16{0};
         }
         // Prologue: E(0), d(0) -> A(0), B(0); E(1), d(1) and the next
-        // trajectory values ready for the loop.
+        // phase values ready for the loop.
         load_fy(0);
         gen_e(0, 0);
         load_d(0);

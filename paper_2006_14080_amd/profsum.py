@@ -156,15 +156,25 @@ def _per_kernel(path, counter):
 KERNEL_SOURCES = ["nudft.hip", "phase.h", "device.h", "internal.h"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and whitespace (string literals in these
+    kernel sources hold no comment markers)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return re.sub(r"\s+", "", text)
+
+
 def kernel_fingerprint() -> str:
-    """sha256 over the sources of the NUDFT kernels (traffic is void once they change)."""
+    """sha256 over the code of the NUDFT kernel sources, comments and
+    whitespace excluded (traffic is void once the code changes)."""
     import hashlib
     import os
     h = hashlib.sha256()
     base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     for n in KERNEL_SOURCES:
-        with open(os.path.join(base, n), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(base, n)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 
