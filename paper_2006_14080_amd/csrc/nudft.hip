@@ -62,7 +62,6 @@ __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
 // LDS planes with K contiguous: A (Ar, Ai); B (Br, Bi, -Bi).  Lanes 0-31 read
 // plane Ar / Br / Bi, lanes 32-63 read Ai / -Bi / Br, four K values per read.
 struct PolF32 {
-    static constexpr bool kInterleave = false;       // FP32 MFMA and VALU do not execute at once (counters)
     static constexpr bool kPresplitA = false;        // forward A staged from the FP32 coil-weighted image
     static constexpr bool kScaled = false;
     static constexpr float kBScale = 1.0f;
@@ -145,7 +144,6 @@ struct PolSplit {
     typedef T vec2 __attribute__((ext_vector_type(2)));
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    static constexpr bool kInterleave = true;        // producers run between the MFMAs (mma_with)
     static constexpr bool kPresplitA = true;         // forward A pre-split into operand chunks once per call
     static constexpr bool kScaled = Scaled;
     static constexpr float kBScale = Scaled ? 16384.0f : 1.0f;   // phases (|e| <= 1) -> [-2^14, 2^14]
