@@ -526,31 +526,35 @@ __global__ __launch_bounds__(256) void k_adj_scale(const NudftTable tab) {
 // (then y) offset, with the reduction of phase.h, i.e. the values the adjoint
 // would otherwise form per step; one thread per table element.  Filled once
 // per trajectory (once per solve).
-__global__ __launch_bounds__(256) void k_adj_phases(const NudftTable tab) {
-    int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int k = 0;
-    for (; k < tab.nitems; ++k) {
-        const NudftItem& c = tab.it[k];
-        const int64_t n = adj_table_elems(c.nx, c.ny, c.nk, c.traj_bs ? c.nb : 1);
-        if (g < n) break;
-        g -= n;
-    }
-    if (k >= tab.nitems) return;
-    const NudftItem& it = tab.it[k];
-    const int64_t nx = it.nx, ny = it.ny;
-    const int64_t per = it.nk * (nx + ny);                // elements per trajectory
-    const int64_t bt = g / per;
-    int64_t r = g - bt * per;
-    const double* traj = it.traj + bt * it.traj_bs;
-    if (r < it.nk * nx) {
-        const int64_t kk = r / nx;
-        const int x = (int)(r - kk * nx);
-        it.ephx[bt * it.ephx_bs + r] = phase_pos(traj[2 * kk] * kQuarterTurnsPerRad, (double)(x - it.nx / 2));
-    } else {
-        r -= it.nk * nx;
-        const int64_t kk = r / ny;
-        const int y = (int)(r - kk * ny);
-        it.ephy[bt * it.ephy_bs + r] = phase_pos(traj[2 * kk + 1] * kQuarterTurnsPerRad, (double)(y - it.ny / 2));
+__global__ __launch_bounds__(256) void k_adj_phases(const NudftTable tab, int64_t total) {
+    // Grid-stride: any table size is covered by a bounded grid.
+    for (int64_t g0 = (int64_t)blockIdx.x * 256 + threadIdx.x; g0 < total; g0 += (int64_t)gridDim.x * 256) {
+        int64_t g = g0;
+        int k = 0;
+        for (; k < tab.nitems; ++k) {
+            const NudftItem& c = tab.it[k];
+            const int64_t n = adj_table_elems(c.nx, c.ny, c.nk, c.traj_bs ? c.nb : 1);
+            if (g < n) break;
+            g -= n;
+        }
+        if (k >= tab.nitems) return;
+        const NudftItem& it = tab.it[k];
+        const int64_t nx = it.nx, ny = it.ny;
+        const int64_t per = it.nk * (nx + ny);            // elements per trajectory
+        const int64_t bt = g / per;
+        int64_t r = g - bt * per;
+        const double* traj = it.traj + bt * it.traj_bs;
+        if (r < it.nk * nx) {
+            const int64_t kk = r / nx;
+            const int x = (int)(r - kk * nx);
+            it.ephx[bt * it.ephx_bs + r] = phase_pos(traj[2 * kk] * kQuarterTurnsPerRad, (double)(x - it.nx / 2));
+        } else {
+            r -= it.nk * nx;
+            const int64_t kk = r / ny;
+            const int y = (int)(r - kk * ny);
+            it.ephy[bt * it.ephy_bs + r] =
+                phase_pos(traj[2 * kk + 1] * kQuarterTurnsPerRad, (double)(y - it.ny / 2));
+        }
     }
 }
 
@@ -1413,7 +1417,8 @@ hipError_t launch_adj_phases(const NudftTable& t, hipStream_t s) {
     for (int i = 0; i < t.nitems; ++i)
         n += adj_table_elems(t.it[i].nx, t.it[i].ny, t.it[i].nk, t.it[i].traj_bs ? t.it[i].nb : 1);
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_phases, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, t);
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)1 << 20);
+    hipLaunchKernelGGL(k_adj_phases, dim3((unsigned)blocks), dim3(256), 0, s, t, n);
     return hipGetLastError();
 }
 
