@@ -77,19 +77,30 @@ struct PolF32 {
             *reinterpret_cast<float4*>(im + j) = make_float4(v[j].y, v[j + 1].y, v[j + 2].y, v[j + 3].y);
         }
     }
+    // A stage row, K values 4h..4h+3 only (re and im planes).
+    __device__ __forceinline__ static void store_a_half(char* st, int row, int rows, int h, const float2* v) {
+        float* re = reinterpret_cast<float*>(st) + row * RS + 4 * h;
+        float* im = re + rows * RS;
+        *reinterpret_cast<float4*>(re) = make_float4(v[0].x, v[1].x, v[2].x, v[3].x);
+        *reinterpret_cast<float4*>(im) = make_float4(v[0].y, v[1].y, v[2].y, v[3].y);
+    }
+    // B stages of BC columns: planes Br, Bi, -Bi of [BC][RS] floats.
+    template <int BC>
+    static constexpr int bbytes() { return 3 * BC * RS * 4; }
+    template <int BC = 64>
     __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
         float* p = reinterpret_cast<float*>(st) + col * RS + kp;
         *reinterpret_cast<float2*>(p) = make_float2(e0.x, e1.x);
-        *reinterpret_cast<float2*>(p + 64 * RS) = make_float2(e0.y, e1.y);
-        *reinterpret_cast<float2*>(p + 128 * RS) = make_float2(-e0.y, -e1.y);
+        *reinterpret_cast<float2*>(p + BC * RS) = make_float2(e0.y, e1.y);
+        *reinterpret_cast<float2*>(p + 2 * BC * RS) = make_float2(-e0.y, -e1.y);
     }
-    template <int NT>
+    template <int NT, int BC = 64>
     __device__ __forceinline__ static void mma(const char* a, const char* b, int arow0, int bcol0, int lane,
                                                int ntile, floatx16 (&acc_re)[NT], floatx16 (&acc_im)[NT]) {
         const int h = lane >> 5, l32 = lane & 31;
         const float* ap = reinterpret_cast<const float*>(a) + (h * kRows + arow0 + l32) * RS;
-        const float* bre = reinterpret_cast<const float*>(b) + ((h ? 2 : 0) * 64 + bcol0 + l32) * RS;
-        const float* bim = reinterpret_cast<const float*>(b) + ((h ? 0 : 1) * 64 + bcol0 + l32) * RS;
+        const float* bre = reinterpret_cast<const float*>(b) + ((h ? 2 : 0) * BC + bcol0 + l32) * RS;
+        const float* bim = reinterpret_cast<const float*>(b) + ((h ? 0 : 1) * BC + bcol0 + l32) * RS;
         // A wave with no live row tile skips the stage; otherwise all NT tiles
         // run (rows past the valid range hold zeros) as one branch-free burst.
         if (__builtin_amdgcn_readfirstlane(ntile) == 0) return;
@@ -204,8 +215,11 @@ struct PolSplit {
     }
     // B column col, complex K values kp and kp+1 (kp even): words kp&3 and
     // (kp&3)+1 of the hi and lo chunks of both variants.
+    template <int BC>
+    static constexpr int bbytes() { return 2 * kChunks * BC * 16; }
+    template <int BC = 64>
     __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
-        store_b_words<64>(st, col, kp, split_b(e0), split_b(e1));
+        store_b_words<BC>(st, col, kp, split_b(e0), split_b(e1));
     }
     // [Br, -Bi] words of one B value (phases carry the kBScale factor).
     __device__ __forceinline__ static Words split_b(float2 e) { return split2(e.x * kBScale, -e.y * kBScale); }
@@ -799,240 +813,25 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: tile = (slice, split, 32 y rows, 64 x columns); GEMM rows are
-// (coil, y) for a group of 8 coils per pass.  Launched for the FP32 form,
-// whose matrix instructions do not run alongside vector work, so its
-// producers simply follow each MFMA burst; the split forms use nudft_adj8.
-// ---------------------------------------------------------------------------
-template <class P, int NT>
-__global__ __launch_bounds__(kThreads, 2) void nudft_adj(const NudftTable tab) {
-    __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + P::kBBytes)];
-    __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC + 2];   // conj(Ey) for the next A (padded rows)
-    __shared__ float sUnscale[2 * kNT];                                       // split-FP16: per coil of the group
-    char* const sA0 = smem;
-    char* const sB0 = smem + 2 * P::kABytes;
-
-    const int tile = xcd_remap(blockIdx.x, tab.total_tiles);
-    const NudftItem& it = tab.it[find_item(tab, tile)];
-    const int nx = it.nx, ny = it.ny, nc = it.nc;
-    const int64_t nk = it.nk;
-    // Pixel tiles vary fastest (y blocks, then x blocks), then sample splits:
-    // the workgroups running together on one XCD work on the same split, so
-    // they read the same phase-table rows (and data) in step through its L2.
-    int local = tile - it.tile_begin;
-    const int nxb = (nx + kAdjCols - 1) / kAdjCols, nyb = (ny + kAdjRows - 1) / kAdjRows;
-    const int yb = local % nyb;
-    local /= nyb;
-    const int xb = local % nxb;
-    local /= nxb;
-    const int sp = local % it.ksplit;
-    const int b = local / it.ksplit;
-    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
-
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1, h = lane >> 5, l32 = lane & 31;
-    const int x0 = xb * kAdjCols, y0 = yb * kAdjRows;
-    const int64_t npix = (int64_t)nx * ny;
-    const float2* sm = it.smaps + b * it.smaps_bs;
-    const float2* dat = it.data + (int64_t)b * nc * nk;
-    const int64_t kbeg = (int64_t)sp * it.kper;
-    const int64_t kend = min(nk, kbeg + it.kper);
-    const int nsteps = (int)ceil_div(kend - kbeg, KC);
-    const int klast = (int)(kend - kbeg - 1);             // last sample of the split, relative
-    // Phase rows of the split's samples (tables filled by k_adj_phases).
-    const float2* phx = it.ephx + b * it.ephx_bs + kbeg * nx;
-    const float2* phy = it.ephy + b * it.ephy_bs + kbeg * ny;
-    const int32_t* aexp = nullptr;
-    if constexpr (P::kScaled) aexp = adj_scale_exp(it.part, nx, ny, nc, it.nb, it.ksplit);
-
-    // Producer roles.
-    const int ey = tid & 31, ek = tid >> 5;              // E: (y, k)
-    const int bx = tid & 63, bk = (tid >> 6) * 2;        // B: (x, k pair)
-    const int ac = tid >> 5, ay = tid & 31;              // A: (coil, y)
-    const bool ey_ok = y0 + ey < ny;
-    const bool bx_ok = x0 + bx < nx;
-    const int yc = ey_ok ? y0 + ey : ny - 1;             // in-bounds table columns
-    const int xc = bx_ok ? x0 + bx : nx - 1;
-    const int xe = x0 + wn * 32 + l32;                   // epilogue column
-
-    // Coils run in groups of 2 * NT, split between the two row-waves (NT coils
-    // each); the host picks NT per coil count so the groups are even
-    // (e.g. 12 coils = 2 groups of 6, NT = 3).
-    constexpr int nt = NT;
-    constexpr int gsz = 2 * NT;
-    const int ncgroups = (nc + gsz - 1) / gsz;
-    for (int gi = 0, g0 = 0; g0 < nc; ++gi, g0 += gsz) {
-        const int ncg = min(gsz, nc - g0);
-        const int nvalid = max(0, min(nt, ncg - wm * nt));
-        // Rows of coils past the group's end (a_ok false) read coil g0 and
-        // feed only accumulator tiles that the epilogue never reads.
-        const bool a_ok = ac < ncg;
-        const float2* drow = dat + (int64_t)(g0 + (a_ok ? ac : 0)) * nk + kbeg;
-        float2 dreg[KC];
-
-        // Split-FP16: W rows of coil ac carry the scale k_adj_scale chose for
-        // this coil and sample split.
-        float ascale = 1.0f;
-        if constexpr (P::kScaled) {
-            const int se = a_ok ? aexp[((int64_t)b * nc + g0 + ac) * it.ksplit + sp] : 0;
-            ascale = ldexpf(1.0f, se);
-            if (ay == 0 && ac < gsz) sUnscale[ac] = ldexpf(1.0f, -se);
-        }
-
-        // Loads are unconditional from clamped (in-bounds) indices; samples past
-        // the split end are masked when staged, so no load sits in a branch.
-        // Sample indices relative to the split start fit in 32 bits.  Steps
-        // wholly inside the split load straight (one address, immediate
-        // offsets); the last step clamps to the split's last sample.
-        auto load_d = [&](int s) {
-            if (s * KC + KC - 1 <= klast) {
-                const float2* p = drow + s * KC;
-#pragma unroll
-                for (int j = 0; j < KC; ++j) dreg[j] = p[j];
-            } else {
-#pragma unroll
-                for (int j = 0; j < KC; ++j) dreg[j] = drow[min(s * KC + j, klast)];
-            }
-        };
-        // Phases are prefetched one step ahead of their use: fx0/fx1 for the
-        // next B stage, fy for the E tile after that (rows clamped to the
-        // split's last sample; those samples are masked when staged).
-        float2 fx0, fx1, fy;
-        auto load_fx = [&](int s) {
-            const int k = s * KC + bk;
-            fx0 = phx[(int64_t)min(k, klast) * nx + xc];
-            fx1 = phx[(int64_t)min(k + 1, klast) * nx + xc];
-        };
-        auto load_fy = [&](int s) {
-            fy = phy[(int64_t)min(s * KC + ek, klast) * ny + yc];
-        };
-        auto gen_e = [&](int st, int s) {
-            float2 e = fy;
-            if (!(ey_ok && s * KC + ek <= klast)) e = make_float2(0.f, 0.f);
-            sE[st][ey][ek] = e;
-        };
-        auto gen_b = [&](int st, int s) {
-            const int k = s * KC + bk;
-            float2 e0 = fx0, e1 = fx1;
-            if (!(bx_ok && k <= klast)) e0 = make_float2(0.f, 0.f);
-            if (!(bx_ok && k + 1 <= klast)) e1 = make_float2(0.f, 0.f);
-            P::store_b(sB0 + st * P::kBBytes, bx, bk, e0, e1);
-        };
-        auto gen_a = [&](int st, int est) {
-            float2 w[KC];
-#pragma unroll
-            for (int j = 0; j < KC; j += 2) {
-                const float4 e2 = *reinterpret_cast<const float4*>(&sE[est][ay][j]);
-                w[j] = cmul(dreg[j], make_float2(e2.x, e2.y));
-                w[j + 1] = cmul(dreg[j + 1], make_float2(e2.z, e2.w));
-                if constexpr (P::kScaled) {
-                    w[j] = cscale(w[j], ascale);
-                    w[j + 1] = cscale(w[j + 1], ascale);
-                }
-            }
-            P::store_a(sA0 + st * P::kABytes, ac * 32 + ay, w);
-        };
-
-        floatx16 acc_re[NT], acc_im[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            acc_re[t] = floatx16{0};
-            acc_im[t] = floatx16{0};
-        }
-        // Prologue: E(0), d(0) -> A(0), B(0); E(1), d(1) and the next
-        // phase values ready for the loop.
-        load_fy(0);
-        gen_e(0, 0);
-        load_d(0);
-        load_fx(0);
-        __syncthreads();
-        gen_a(0, 0);
-        gen_b(0, 0);
-        load_fx(1);
-        if (nsteps > 1) {
-            load_fy(1);
-            gen_e(1, 1);
-            load_d(1);
-        }
-        load_fy(2);
-        __syncthreads();
-        for (int s = 0; s < nsteps; ++s) {
-            const int cur = s & 1;
-            P::template mma<NT>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32), wn * 32, lane, nvalid,
-                   acc_re, acc_im);
-            if (s + 1 < nsteps) {
-                gen_a(cur ^ 1, cur ^ 1);              // W(s+1) from d(s+1) and E(s+1)
-                if (s + 2 < nsteps) load_d(s + 2);
-                gen_b(cur ^ 1, s + 1);                // uses fx(s+1)
-                if (s + 2 < nsteps) gen_e(cur, s + 2);   // uses fy(s+2)
-                load_fx(s + 2);
-                load_fy(s + 3);
-            }
-            __syncthreads();
-        }
-        // Coil combine of this group: sum_g conj(s_g[y][x]) X_g[y][x], then the
-        // two row-waves (coils 0-3 and 4-7 of the group) meet through LDS and
-        // the group's partial image is written for the fixed-order reduction.
-        float2 part[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) part[i] = make_float2(0.f, 0.f);
-        if (xe < nx) {
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                if (t < nvalid) {
-                    const int g = g0 + wm * nt + t;
-                    const float2* sg = sm + (int64_t)g * npix;
-                    // split-FP16: phase scale, then this coil's data scale
-                    constexpr float kInvB = 1.0f / P::kBScale;
-                    float us = 1.0f;
-                    if constexpr (P::kScaled) us = sUnscale[wm * nt + t];
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int y = y0 + (i >> 2) * 8 + h * 4 + (i & 3);
-                        if (y < ny)
-                            part[i] = cadd(part[i], cmulc(sg[(int64_t)y * nx + xe],
-                                                          make_float2(acc_re[t][i] * kInvB * us,
-                                                                      acc_im[t][i] * kInvB * us)));
-                    }
-                }
-            }
-        }
-        float2* red = reinterpret_cast<float2*>(smem);   // 2 (wn) x 16 x 64 complex
-        if (wm == 1) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) red[(wn * 16 + i) * 64 + lane] = part[i];
-        }
-        __syncthreads();
-        if (wm == 0 && xe < nx) {
-            const int plane = sp * ncgroups + gi;
-            float2* out = it.part + ((int64_t)plane * it.nb + b) * npix;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int y = y0 + (i >> 2) * 8 + h * 4 + (i & 3);
-                if (y < ny) out[(int64_t)y * nx + xe] = cadd(part[i], red[(wn * 16 + i) * 64 + lane]);
-            }
-        }
-    }
-}
-
-
-// ---------------------------------------------------------------------------
-// Adjoint of the split forms: 8 waves over a 32 y x 128 x pixel tile (one
-// workgroup per CU).  The GEMM rows are (coil, y) as in nudft_adj; doubling
-// the x extent lets every W = d conj(Ey) value feed twice the MFMAs, which
-// cuts the vector work per matrix instruction by about a quarter.  Each
-// thread forms half a W row (4 K values) and stages two conj(Ex) values and
-// one conj(Ey) value per step from the phase tables (waves 4-7 stage the same
-// conj(Ey) values as waves 0-3 into the tile's padding column, so every wave
-// does the same work and the loop has no role branch).  Steps whose
-// look-ahead loads are whole steps run with the producers interleaved between
-// the MFMA groups; the split's last steps take a plain loop.
+// Adjoint: tile = (slice, sample split, 32 y rows, 128 x columns), 8 waves
+// (2 row x 4 column waves, one workgroup per CU).  GEMM rows are (coil, y)
+// for a group of 2 NT coils per pass: A = W = d conj(Ey), B = conj(Ex), K =
+// samples of the split; the epilogue forms sum_g conj(s_g) X_g and writes the
+// group's partial image for the fixed-order reduction.  The 128-column tile
+// lets every W value feed twice the MFMAs of a 64-column one, halving the
+// vector work of W per matrix instruction.  Each thread forms half a W row
+// (4 K values) and stages two conj(Ex) values and one conj(Ey) value per step
+// from the phase tables (waves 4-7 stage the same conj(Ey) values as waves
+// 0-3 into the tile's padding column, so every wave does the same work and
+// the loop has no role branch).  In the split forms, steps whose look-ahead
+// loads are whole steps run with the producers interleaved between the MFMA
+// groups and the split's last steps take a plain loop; FP32 takes the plain
+// loop throughout (its matrix instructions do not run alongside vector work).
 // ---------------------------------------------------------------------------
 template <class P, int NT>
 __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab) {
     constexpr int BC = kAdjCols8;
-    constexpr int kBBytes8 = 2 * P::kChunks * BC * 16;
+    constexpr int kBBytes8 = P::template bbytes<BC>();
     __shared__ __attribute__((aligned(16))) char smem[2 * (P::kABytes + kBBytes8)];
     __shared__ __attribute__((aligned(16))) float2 sE[2][kAdjRows][KC + 2];   // conj(Ey); column KC takes duplicates
     __shared__ float sUnscale[2 * kNT];
@@ -1131,9 +930,8 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
             const int k = s * KC + bk;
             const float m0 = (bx_ok && k <= klast) ? 1.f : 0.f;
             const float m1 = (bx_ok && k + 1 <= klast) ? 1.f : 0.f;
-            P::template store_b_words<BC>(sB0 + st * kBBytes8, bx, bk,
-                                          P::split_b(make_float2(fx0.x * m0, fx0.y * m0)),
-                                          P::split_b(make_float2(fx1.x * m1, fx1.y * m1)));
+            P::template store_b<BC>(sB0 + st * kBBytes8, bx, bk, make_float2(fx0.x * m0, fx0.y * m0),
+                                    make_float2(fx1.x * m1, fx1.y * m1));
         };
         // W of this thread's row and K half: d conj(Ey) (with the coil's scale).
         auto gen_a = [&](int st, int est) {
@@ -1175,8 +973,11 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
         load_fy(2);
         __syncthreads();
         int s = 0;
+        // Steady state of the split forms: every look-ahead load is a whole
+        // step, no branch, producers interleaved.  (FP32 matrix instructions
+        // do not run alongside vector work, so FP32 takes the plain loop.)
+        if constexpr (P::kPresplitA)
         for (; s < nsteps - 3; ++s) {
-            // Steady state: every look-ahead load is a whole step, no branch.
             const int cur = s & 1;
             float2 w[4];
             typename P::Words r0;
@@ -1377,15 +1178,6 @@ hipError_t fwd_variant(const NudftTable& t, int nt, hipStream_t s) {
 }
 
 template <class P>
-hipError_t adj_variant(const NudftTable& t, int nt, hipStream_t s) {
-    const dim3 g(t.total_tiles), b(kThreads);
-    if (nt == 2) hipLaunchKernelGGL((nudft_adj<P, 2>), g, b, 0, s, t);
-    else if (nt == 3) hipLaunchKernelGGL((nudft_adj<P, 3>), g, b, 0, s, t);
-    else hipLaunchKernelGGL((nudft_adj<P, 4>), g, b, 0, s, t);
-    return hipGetLastError();
-}
-
-template <class P>
 hipError_t adj8_variant(const NudftTable& t, int nt, hipStream_t s) {
     const dim3 g(t.total_tiles), b(kThreads8);
     if (nt == 2) hipLaunchKernelGGL((nudft_adj8<P, 2>), g, b, 0, s, t);
@@ -1432,9 +1224,8 @@ hipError_t launch_nudft_adjoint(const NudftTable& t, int precision, hipStream_t 
         if (e != hipSuccess) return e;
     }
     if (precision == MRI_FP32)
-        return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); },
-                            [](const NudftItem& it) { return (int64_t)it.ntiles; },
-                            [&](const NudftTable& sub, int nt) { return adj_variant<PolF32>(sub, nt, s); });
+        return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); }, adj8_tiles,
+                            [&](const NudftTable& sub, int nt) { return adj8_variant<PolF32>(sub, nt, s); });
     return launch_by_nt(t, [](const NudftItem& it) { return adj_nt(it.nc); }, adj8_tiles,
                         [&](const NudftTable& sub, int nt) {
                             return precision == MRI_BF16X3 ? adj8_variant<PolBF16>(sub, nt, s)
