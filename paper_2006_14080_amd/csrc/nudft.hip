@@ -757,10 +757,14 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         }
 
         // Epilogue: sum_y T[y][k] Ey[k][y] over this pass's rows.  Rows of a
-        // lane are ybase + 32 t + 8 q + r (r < 4); the phase is built as
-        // Ey(ybase) * E(32 t) * E(8 q) * E(r) from ten accurate factors.
+        // lane are ybase + 32 t + 8 q + r (r < 4) and the phase factors as
+        // Ey(ybase) E(32 t) E(8 q) E(r) (ten accurate factors), so the sum is
+        // taken in Horner form, innermost over r:
+        //   Ey(ybase) sum_t E(32 t) sum_q E(8 q) sum_r E(r) T[ybase + 32 t + 8 q + r].
+        // Rows past ny within a live tile hold zero accumulators (their A rows
+        // are zero), so no row test is needed.
         // Split-FP16: the phase scale and each row's pre-pass scale are undone
-        // here, one after the other (each factor a normal power of two).
+        // first, one after the other (each factor a normal power of two).
         constexpr float kInvB = 1.0f / P::kBScale;
         float2 part = make_float2(0.f, 0.f);
         if (e_ok && nvalid > 0) {
@@ -771,7 +775,6 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             const int ybase = wrow0 + h * 4 - yh;
             const float2 e0 = phase_neg(fy4, (double)ybase);
             float2 f1[4], f8[4], f32[NT];
-            f1[0] = f8[0] = f32[0] = make_float2(1.f, 0.f);
 #pragma unroll
             for (int j = 1; j < 4; ++j) {
                 f1[j] = phase_neg(fy4, (double)j);
@@ -779,28 +782,27 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             }
 #pragma unroll
             for (int j = 1; j < NT; ++j) f32[j] = phase_neg(fy4, (double)(32 * j));
+            float2 st = make_float2(0.f, 0.f);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 if (t < nvalid) {
-                    const float2 et = cmul(e0, f32[t]);
+                    float2 sq = make_float2(0.f, 0.f);
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float2 etq = cmul(et, f8[q]);
                         float4 rs4 = make_float4(1.f, 1.f, 1.f, 1.f);
                         if constexpr (P::kScaled) rs4 = *reinterpret_cast<const float4*>(rsc + t * 32 + q * 8);
                         const float rs[4] = {rs4.x, rs4.y, rs4.z, rs4.w};
+                        float2 sr = make_float2(acc_re[t][q * 4] * kInvB * rs[0], acc_im[t][q * 4] * kInvB * rs[0]);
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int i = q * 4 + r;
-                            const int y = wrow0 + t * 32 + q * 8 + h * 4 + r;
-                            if (y < ny)
-                                part = cadd(part, cmul(make_float2(acc_re[t][i] * kInvB * rs[r],
-                                                                   acc_im[t][i] * kInvB * rs[r]),
-                                                       cmul(etq, f1[r])));
-                        }
+                        for (int r = 1; r < 4; ++r)
+                            sr = cfma(f1[r], make_float2(acc_re[t][q * 4 + r] * kInvB * rs[r],
+                                                         acc_im[t][q * 4 + r] * kInvB * rs[r]), sr);
+                        sq = q == 0 ? sr : cfma(f8[q], sr, sq);
                     }
+                    st = t == 0 ? sq : cfma(f32[t], sq, st);
                 }
             }
+            part = cmul(e0, st);
         }
         part.x += __shfl_xor(part.x, 32, 64);
         part.y += __shfl_xor(part.y, 32, 64);
