@@ -41,6 +41,7 @@ constexpr int kNT = 4;                    // 32-row MFMA tiles per wave
 constexpr int kRows = 2 * kNT * 32;       // GEMM rows per pass (256)
 constexpr int KC = kKStep;                // complex K values per stage (8)
 constexpr int RS = KC + 4;                // LDS row stride in floats: conflict-free 16-byte reads
+constexpr int kXAnchor = 8;               // forward: K-steps per exactly generated step phase
 
 __device__ __forceinline__ int find_item(const NudftTable& t, int tile) {
     int i = 0;
@@ -611,6 +612,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
     const double fx4 = p_ok ? traj[2 * (k0 + pc)] * kQuarterTurnsPerRad : 0.0;
     const float2 w0 = phase_neg(fx4, (double)pj);
     const float2 w1 = phase_neg(fx4, (double)(pj + 1));
+    const float2 wk = phase_neg(fx4, (double)KC);      // one K-step
     // Epilogue: this lane's sample column.
     const int64_t ke = k0 + wn * 32 + l32;
     const bool e_ok = ke < nk;
@@ -678,14 +680,17 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
         auto wait_a = [&]() {
             if constexpr (P::kPresplitA) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         };
+        // B stage s: Ex[k][s KC + pj + j] = xb(s) w_j with the step base
+        // xb(s) = Ex(s KC - nx/2).  Steps are staged in order within a pass, so
+        // xb advances by one factor E(KC) per step and is regenerated with the
+        // FP64 reduction every kXAnchor steps (at most kXAnchor - 1 roundings
+        // of drift).  Samples past nk (fx4 = 0) stage unit phases; their
+        // outputs are never stored.
+        float2 xb = make_float2(1.f, 0.f);
         auto store_b = [&](int st, int s) {
-            float2 e0 = make_float2(0.f, 0.f), e1 = e0;
-            if (p_ok) {
-                const float2 base = phase_neg(fx4, (double)(s * KC - xh));
-                e0 = cmul(base, w0);
-                e1 = cmul(base, w1);
-            }
-            P::store_b(sB0 + st * P::kBBytes, pc, pj, e0, e1);
+            if (s % kXAnchor == 0) xb = phase_neg(fx4, (double)(s * KC - xh));
+            else xb = cmul(xb, wk);
+            P::store_b(sB0 + st * P::kBBytes, pc, pj, cmul(xb, w0), cmul(xb, w1));
         };
 
         floatx16 acc_re[NT], acc_im[NT];
@@ -758,8 +763,10 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
 
         // Epilogue: sum_y T[y][k] Ey[k][y] over this pass's rows.  Rows of a
         // lane are ybase + 32 t + 8 q + r (r < 4) and the phase factors as
-        // Ey(ybase) E(32 t) E(8 q) E(r) (ten accurate factors), so the sum is
-        // taken in Horner form, innermost over r:
+        // Ey(ybase) E(32 t) E(8 q) E(r); Ey(ybase), E(1), E(8) and E(32) are
+        // generated with the FP64 argument reduction and the other powers are
+        // their products (a few FP32 roundings each).  The sum is taken in
+        // Horner form, innermost over r:
         //   Ey(ybase) sum_t E(32 t) sum_q E(8 q) sum_r E(r) T[ybase + 32 t + 8 q + r].
         // Rows past ny within a live tile hold zero accumulators (their A rows
         // are zero), so no row test is needed.
@@ -775,13 +782,16 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             const int ybase = wrow0 + h * 4 - yh;
             const float2 e0 = phase_neg(fy4, (double)ybase);
             float2 f1[4], f8[4], f32[NT];
+            f1[1] = phase_neg(fy4, 1.0);
+            f8[1] = phase_neg(fy4, 8.0);
 #pragma unroll
-            for (int j = 1; j < 4; ++j) {
-                f1[j] = phase_neg(fy4, (double)j);
-                f8[j] = phase_neg(fy4, (double)(8 * j));
+            for (int j = 2; j < 4; ++j) {
+                f1[j] = cmul(f1[j - 1], f1[1]);
+                f8[j] = cmul(f8[j - 1], f8[1]);
             }
+            if constexpr (NT > 1) f32[1] = phase_neg(fy4, 32.0);
 #pragma unroll
-            for (int j = 1; j < NT; ++j) f32[j] = phase_neg(fy4, (double)(32 * j));
+            for (int j = 2; j < NT; ++j) f32[j] = cmul(f32[j - 1], f32[1]);
             float2 st = make_float2(0.f, 0.f);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
