@@ -3,8 +3,10 @@
 //
 // Both operators use the separable phase of Alg. 1,
 //   exp(-i (w0 x + w1 y)) = Ex[k][x] * Ey[k][y],
-// and never store a phase matrix: every phase tile is generated in LDS from
-// the trajectory (phase.h), one K-step ahead of the matrix cores.
+// and never store a phase matrix: every phase tile is formed in LDS one
+// K-step ahead of the matrix cores, from the trajectory (forward, phase.h) or
+// from the separable factor tables built from it once per trajectory
+// (adjoint, k_adj_phases).
 //
 // Forward, per slice b and coil g:  T[y][k] = sum_x I[y][x] Ex[k][x] with
 // I = s_g (.) x_b (formed by a pre-pass, k_coil_weight), then
