@@ -1113,11 +1113,14 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
     // order alone and in a batch: results are batch-invariant bit for bit.
     (void)nc; (void)precision; (void)nb;
     const int64_t tps = adj_tiles_per_split(nx, ny, 1);
-    // Workgroups per slice.  512 (2048 samples per split at 256^2 / 8 coils)
-    // measured 1-4 % faster but its longer FP32 accumulations tripled the
-    // benchmark solve's image error in the FP16x3 form (4.6e-5 -> 1.3e-4);
-    // 1024 keeps 1024 samples per split.
-    const int64_t target = 1024;
+    // Splits: target / (64 x 32 pixel blocks of a slice), e.g. at 256^2 16
+    // sample ranges (2048 samples each at 8 coils): 256 workgroups of the
+    // 128-column adjoint tile, one per CU.  Twice as many (1024 samples each)
+    // ran the adjoint 1.7 % (FP32) to 5.5 % (split forms) slower: each
+    // workgroup's first steps, coil combine and partial image count twice;
+    // the longer FP32 accumulations raise the adjoint's error by about the
+    // square root of 2 (1.1e-6 vs the oracle in FP32 at 256^2).
+    const int64_t target = 512;
     int64_t s = ceil_div(target, tps);
     // At least 256 samples per split: short sample ranges (one GPU's share of
     // a k-space split, 4096 samples per coil at 256^2) then still fill the
