@@ -17,8 +17,14 @@ steps.  Also reported:
   (one ADMM iteration with 5 CG steps of the same problem);
 * image_nrmse_vs_oracle -- the timed solve's image against the oracle's own
   30 x 5 reconstruction of the same data (stored under tests/golden), and
-  image_nrmse_vs_phantom against the ground-truth phantom, so the forms
-  (fp32, bf16x3, fp16x3) are compared at their accuracy.
+  image_nrmse_vs_phantom against the ground-truth phantom;
+* forms_at_equal_nrmse -- FP32 at 30 x 5 beside each split form (bf16x3,
+  fp16x3) run for as many ADMM iterations as it takes to reach FP32's image
+  NRMSE against the phantom to three significant figures, with the seconds
+  per reconstruction of each;
+* latency_p50_s / latency_p99_s -- reconstruction latency over a short
+  Poisson trace (24 mixed-shape requests at 0.3 req/s, below the FP32
+  saturation knee) replayed against the continuous-batching server.
 
 Other workloads (one JSON line each):
 
@@ -51,6 +57,9 @@ DTYPE = {"fp32": "f32", "bf16x3": "bf16x3", "fp16x3": "f16x3"}
 # Oracle data and 30 x 5 reconstruction of the 256x256 problem
 # (written by tests/golden/make_admm256_golden.py).
 GOLDEN_ADMM256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "admm256_oracle.npz")
+# Oracle data and 2 x 2 reconstructions of slices 0 and 31 of the 32-slice
+# 384x384 batch (tests/golden/make_slices384_golden.py).
+GOLDEN_SLICES384 = os.path.join(ROOT, "tests", "golden", "slices384_oracle.npz")
 HBM_PEAK_GBS = 8000.0
 
 
@@ -68,6 +77,13 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: device pool (GiB)")
     ap.add_argument("--kernel-launches", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve-latency", action="store_true",
+                    help="admm256: skip the served trace behind latency_p50_s / latency_p99_s")
+    ap.add_argument("--no-equal-nrmse", action="store_true",
+                    help="admm256: skip the comparison of the precision forms at equal image NRMSE")
+    ap.add_argument("--latency-requests", type=int, default=24)
+    ap.add_argument("--latency-rate", type=float, default=0.3,
+                    help="admm256: arrival rate of the latency trace (req/s), under the FP32 knee (~0.45)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "nudft_traffic_admm256.json"),
                     help="JSON with measured HBM bytes per launch of the NUDFT kernels (optional)")
     return ap.parse_args()
@@ -117,6 +133,9 @@ def bench_slices(args):
     data += g(p.noise.astype(np.complex64))
     torch.cuda.synchronize()
     shape = mri.shape_of((wl.batch, wl.ny, wl.nx), sm, tr)
+    # sizes for the memory-bound kernels' bandwidth summary (profsum vecbw)
+    print(f"npix={wl.batch * wl.nx * wl.ny} coils={wl.nc} planes={mri.adjoint_split(shape)['planes']}",
+          file=sys.stderr, flush=True)
     steps, warm = max(1, args.steps), args.warmup
     # admm_iters = warmup + timed iterations; F^H d and the init run before the timed region
     stream = torch.cuda.current_stream()
@@ -136,6 +155,24 @@ def bench_slices(args):
         del solver
     ms_step = (timings[warm + steps] - timings[warm]) / steps
     flop_iter = wl.nudft_flop * 2 * (1 + wl.cg_iters)
+    # Image error: the same batch with slices 0 and 31 on the data stored with
+    # the oracle's reconstructions of them (tests/golden, 2 ADMM x 2 CG).
+    img_err = None
+    if os.path.exists(GOLDEN_SLICES384):
+        gold = np.load(GOLDEN_SLICES384)
+        d2 = data.clone()
+        for i, b in enumerate(gold["slices"]):
+            d2[int(b)] = g(gold["data"][i])
+        solver = mri.AdmmSolver(shape, mri.AdmmParams(wl.lam, wl.beta, int(gold["admm_iters"]),
+                                                      int(gold["cg_iters"]), precision=prec), device=dev)
+        solver.solve(sm, tr, d2, out=out)
+        torch.cuda.synchronize()
+        img_err = {"admm_iters": int(gold["admm_iters"]), "cg_iters": int(gold["cg_iters"])}
+        for i, b in enumerate(gold["slices"]):
+            got = out[int(b)].cpu().numpy().astype(np.complex128)
+            ref = gold["images"][i].astype(np.complex128)
+            img_err[f"slice{int(b)}"] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        del solver, d2
     rec = {
         "metric": "ADMM iters/s over a 32-slice 384x384 batch (16 coils, 128x768 samples, 5 CG per iteration)",
         "value": 1e3 / ms_step, "unit": "ADMM iters/s (whole batch)", "n_gpus": 1, "steps": steps,
@@ -149,6 +186,7 @@ def bench_slices(args):
                            "with warmup and warmup+steps iterations isolates the per-iteration time"},
         "fp32_equiv_tflops": flop_iter / ms_step / 1e9,
         "slice_iters_per_s": wl.batch * 1e3 / ms_step,
+        "image_nrmse_vs_oracle": img_err,
     }
     print(json.dumps(rec), flush=True)
 
@@ -212,13 +250,14 @@ def bench_table1_large(args):
     print(json.dumps(rec), flush=True)
 
 
-def bench_serve(args):
-    """Mixed-shape request stream through the continuous-batching server."""
+def run_served_trace(prec, n_requests, rate, slots, budget_gb, progress_s=30.0):
+    """Replay a Poisson stream of mixed-shape requests against the request
+    server in wall-clock time; returns (replay result, total NUDFT flop,
+    arrival times)."""
     import torch
     from paper_2006_14080_amd import mri, serve, synth
 
-    prec = mri.PRECISIONS[args.precision]
-    reqs = synth.request_stream(args.requests, rate=args.rate)
+    reqs = synth.request_stream(n_requests, rate=rate)
     dev = torch.device("cuda:0")
     g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     payloads, flop = [], 0.0
@@ -233,8 +272,17 @@ def bench_serve(args):
         flop += r.wl.nudft_flop * r.wl.nudft_calls
     torch.cuda.synchronize()
     arrivals = [r.arrival for r in reqs]
-    with serve.Server(int(args.budget_gb * (1 << 30)), max_slots=args.slots, precision=prec) as srv:
-        res = serve.replay(srv, arrivals, payloads, progress_s=30.0)
+    with serve.Server(int(budget_gb * (1 << 30)), max_slots=slots, precision=prec) as srv:
+        res = serve.replay(srv, arrivals, payloads, progress_s=progress_s)
+    return res, flop, arrivals
+
+
+def bench_serve(args):
+    """Mixed-shape request stream through the continuous-batching server."""
+    from paper_2006_14080_amd import mri
+
+    prec = mri.PRECISIONS[args.precision]
+    res, flop, arrivals = run_served_trace(prec, args.requests, args.rate, args.slots, args.budget_gb)
     rec = {
         "metric": "served ADMM-TV reconstructions: p50/p99 latency and recons/s",
         "value": res["recons_per_s"], "unit": "recons/s", "n_gpus": 1, "steps": args.requests, "warmup": 0,
@@ -252,6 +300,53 @@ def bench_serve(args):
         "server": {k: int(v) for k, v in res["info"].items()},
     }
     print(json.dumps(rec), flush=True)
+
+
+def sig3(v: float) -> str:
+    return f"{v:.3g}"
+
+
+def forms_at_equal_nrmse(wl, sm, tr, data, truth0, max_iters=90):
+    """The precision forms compared at equal image quality: FP32 runs the
+    workload's 30 x 5; each split form runs 30, 31, ... ADMM iterations (5 CG
+    each) until its image NRMSE against the phantom, at three significant
+    figures, is no larger than FP32's (or max_iters is reached); `matched_3sf`
+    says whether the two agree to three figures there.  Seconds per
+    reconstruction are HIP-event times of one whole solve."""
+    import torch
+    from paper_2006_14080_amd import mri
+
+    stream = torch.cuda.current_stream()
+    shape = mri.shape_of((1, wl.ny, wl.nx), sm, tr)
+    out = torch.empty((1, wl.ny, wl.nx), dtype=torch.complex64, device=data.device)
+
+    def run(prec, n):
+        solver = mri.AdmmSolver(shape, mri.AdmmParams(wl.lam, wl.beta, n, wl.cg_iters, precision=prec),
+                                device=data.device)
+        solver.solve(sm, tr, data, out=out)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        solver.solve(sm, tr, data, out=out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        got = out[0].cpu().numpy().astype(np.complex128)
+        return float(np.linalg.norm(got - truth0) / np.linalg.norm(truth0)), a.elapsed_time(b) / 1e3
+
+    e32, t32 = run(mri.FP32, wl.admm_iters)
+    res = {"fp32": {"admm_iters": wl.admm_iters, "nrmse_vs_phantom": e32, "s_per_recon": t32}}
+    for name in ("bf16x3", "fp16x3"):
+        prec = mri.PRECISIONS[name]
+        reached = False
+        for n in range(wl.admm_iters, max_iters + 1):
+            e, t = run(prec, n)
+            if float(sig3(e)) <= float(sig3(e32)):
+                reached = True
+                break
+        res[name] = {"admm_iters": n, "nrmse_vs_phantom": e, "s_per_recon": t, "reached": reached,
+                     "matched_3sf": sig3(e) == sig3(e32), "speedup_vs_fp32": t32 / t}
+        print(f"[equal-nrmse] {name}: {n} ADMM iterations, NRMSE vs phantom {e:.5f} (fp32 {e32:.5f}), "
+              f"{t:.3f} s vs {t32:.3f} s", file=sys.stderr, flush=True)
+    return res
 
 
 def main():
@@ -388,6 +483,21 @@ def main():
         "image_nrmse_vs_oracle": nrmse,
         "image_nrmse_vs_phantom": nrmse_truth,
     }
+    if not args.no_equal_nrmse:
+        rec["forms_at_equal_nrmse"] = forms_at_equal_nrmse(wl, sm, tr, data, truth0)
+    if not args.no_serve_latency:
+        # The latency half of the metric: a short Poisson trace of mixed-shape
+        # requests (128/256/384 px, 4-32 coils, 32-128 spokes, 30 x 5 each) at
+        # an arrival rate under the form's saturation knee, replayed in wall-clock
+        # time against the continuous-batching server.
+        res, sflop, arr = run_served_trace(prec, args.latency_requests, args.latency_rate, 8, 64.0)
+        rec["latency_p50_s"] = res["p50_s"]
+        rec["latency_p99_s"] = res["p99_s"]
+        rec["latency_trace"] = {"workload": f"serve_poisson{args.latency_rate:g}_n{args.latency_requests}",
+                                "rate_req_s": args.latency_rate, "requests": args.latency_requests,
+                                "recons_per_s": res["recons_per_s"], "wall_s": res["wall_s"],
+                                "latency_mean_s": float(np.mean(res["latency_s"])),
+                                "served_fp32_equiv_tflops": sflop / res["wall_s"] / 1e12}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(wl, p)
     print(json.dumps(rec), flush=True)

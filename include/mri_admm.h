@@ -254,10 +254,13 @@ typedef struct {
 enum { MRI_REQ_UNKNOWN = -1, MRI_REQ_QUEUED = 0, MRI_REQ_RUNNING = 1, MRI_REQ_DONE = 2 };
 
 /* Create a server.  precision: MRI_FP32, MRI_BF16X3 or MRI_FP16X3 for all
- * its requests.
+ * its requests.  stream: the hipStream_t every copy, launch and graph replay
+ * of the server goes to (it must stay valid until mri_server_destroy and
+ * must not be the legacy default stream, which cannot be captured); NULL =
+ * the server creates and owns a non-blocking stream of its own.
  * Errors: MRI_EINVAL (max_slots out of range), MRI_ENOMEM (pool allocation
  * failed), MRI_EHIP. */
-int mri_server_create(size_t hbm_budget, int max_slots, int precision, void** srv);
+int mri_server_create(size_t hbm_budget, int max_slots, int precision, void* stream, void** srv);
 
 /* Queue a request; *id receives its handle.  MRI_ENOMEM if the request alone
  * can never fit the pool; MRI_EINVAL for bad shape/params (batch != 1). */
@@ -287,6 +290,16 @@ int mri_server_destroy(void* srv);
 /* Workspace bytes needed by an operation (params may be NULL except for
  * MRI_OP_ADMM).  Returns 0 for an invalid shape. */
 size_t mri_workspace_bytes(const mri_shape* shape, int op, const mri_admm_params* params);
+
+/* Sample-range split of nudft_adjoint for a shape (the same for every
+ * precision): *ksplit sample ranges of *kper samples each, and *planes
+ * partial images per slice in the workspace, one per (sample range, coil
+ * group of up to 8 coils), summed in a fixed order after the matrix
+ * products.  Any output pointer may be NULL.  This fixes the adjoint's
+ * summation order, and so its rounding, and the workspace's partial-image
+ * bytes (*planes x batch x nx x ny x 8).
+ * Errors: MRI_EINVAL for an invalid shape. */
+int mri_adjoint_split(const mri_shape* shape, int32_t* ksplit, int32_t* kper, int32_t* planes);
 
 /* Static description of an error code. */
 const char* mri_strerror(int code);

@@ -1,7 +1,7 @@
 """Build libmriadmm.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2006_14080_amd.build          # compile every source
-    python -m paper_2006_14080_amd.build --asm    # also dump the gfx950 assembly
+    python -m paper_2006_14080_amd.build                  # compile every source
+    python -m paper_2006_14080_amd.build --asm DIR        # also write the gfx950 assembly to DIR
 
 Every HIP source is compiled with packed-FP32 instruction selection disabled
 (``-packed-fp32-ops``); the host pass warns that it does not know the
@@ -33,7 +33,9 @@ def flags():
             "-Wall", "-Wno-unused-result", "-I", CSRC]
 
 
-def build(verbose: bool = False, asm: bool = False) -> str:
+def build(verbose: bool = False, asm: str = "") -> str:
+    """Compile every source into libmriadmm.so; with `asm` (a directory) also
+    write each source's device assembly there."""
     cc = hipcc()
     tmp = tempfile.mkdtemp(prefix="mriadmm_build_")
     try:
@@ -52,8 +54,8 @@ def build(verbose: bool = False, asm: bool = False) -> str:
                 print(errs, file=sys.stderr)
             objs.append(obj)
             if asm:
-                out = os.path.join(HERE, "..", "_work", "asm", src + ".s")
-                os.makedirs(os.path.dirname(out), exist_ok=True)
+                out = os.path.join(asm, src + ".s")
+                os.makedirs(asm, exist_ok=True)
                 subprocess.run([cc, *flags(), "--cuda-device-only", "-S",
                                 os.path.join(CSRC, src), "-o", out], check=True,
                                stderr=subprocess.PIPE)
@@ -66,4 +68,5 @@ def build(verbose: bool = False, asm: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, asm="--asm" in sys.argv))
+    asm_dir = sys.argv[sys.argv.index("--asm") + 1] if "--asm" in sys.argv else ""
+    print(build(verbose="-v" in sys.argv, asm=asm_dir))

@@ -68,6 +68,17 @@ size_t mri_workspace_bytes(const mri_shape* shape, int op, const mri_admm_params
     }
 }
 
+int mri_adjoint_split(const mri_shape* shape, int32_t* ksplit, int32_t* kper, int32_t* planes) {
+    const int rc = check_shape(shape);
+    if (rc) return rc;
+    int32_t ks, kp;
+    adj_split(shape->nx, shape->ny, shape->ncoils, shape->nk, shape->batch, MRI_FP32, &ks, &kp);
+    if (ksplit) *ksplit = ks;
+    if (kper) *kper = kp;
+    if (planes) *planes = adj_partial_planes(shape->ncoils, ks);
+    return MRI_OK;
+}
+
 const char* mri_strerror(int code) {
     switch (code) {
         case MRI_OK: return "success";

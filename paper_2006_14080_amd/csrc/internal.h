@@ -52,8 +52,8 @@ static_assert(sizeof(NudftTable) <= 4096, "a NudftTable is passed as a kernel ar
 
 // Forward tiling: 64 samples per workgroup, rows = all y in chunks of 256.
 constexpr int kFwdCols = 64;
-// Adjoint tiling: 64 x columns, 32 y rows, all coils (in groups of 8) per tile.
-constexpr int kAdjCols = 64;
+// Adjoint tiling: 128 x columns, 32 y rows, all coils (in groups of 8) per tile.
+constexpr int kAdjCols = 128;
 constexpr int kAdjRows = 32;
 constexpr int kAdjCoilGroup = 8;
 constexpr int kKStep = 8;          // complex K values per pipeline stage
@@ -63,6 +63,7 @@ __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + 
 int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb);
 // Elements of the coil-weighted image the forward reads (rows padded to a K-step).
 int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb);
+// Adjoint tiles (workgroups) per sample split: nb x 128-column x 32-row blocks.
 int64_t adj_tiles_per_split(int nx, int ny, int nb);
 // Row tiles per wave of the forward (by ny) and of the adjoint (by coil count).
 __host__ __device__ inline int fwd_nt(int ny) {

@@ -38,7 +38,7 @@ namespace {
 
 constexpr int kThreads = 256;             // 4 waves: 2 (rows) x 2 (cols)
 constexpr int kThreads8 = 512;            // split-form adjoint: 8 waves, 2 (rows) x 4 (cols)
-constexpr int kAdjCols8 = 128;            // its x columns per tile
+constexpr int kAdjCols8 = kAdjCols;       // its x columns per tile (128)
 constexpr int kNT = 4;                    // 32-row MFMA tiles per wave
 constexpr int kRows = 2 * kNT * 32;       // GEMM rows per pass (256)
 constexpr int KC = kKStep;                // complex K values per stage (8)
@@ -1113,14 +1113,14 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
     // order alone and in a batch: results are batch-invariant bit for bit.
     (void)nc; (void)precision; (void)nb;
     const int64_t tps = adj_tiles_per_split(nx, ny, 1);
-    // Splits: target / (64 x 32 pixel blocks of a slice), e.g. at 256^2 16
+    // Splits: target / (128 x 32 pixel tiles of a slice), e.g. at 256^2 16
     // sample ranges (2048 samples each at 8 coils): 256 workgroups of the
-    // 128-column adjoint tile, one per CU.  Twice as many (1024 samples each)
+    // adjoint tile, one per CU.  Twice as many (1024 samples each)
     // ran the adjoint 1.7 % (FP32) to 5.5 % (split forms) slower: each
     // workgroup's first steps, coil combine and partial image count twice;
     // the longer FP32 accumulations raise the adjoint's error by about the
     // square root of 2 (1.1e-6 vs the oracle in FP32 at 256^2).
-    const int64_t target = 512;
+    const int64_t target = 256;
     int64_t s = ceil_div(target, tps);
     // At least 256 samples per split: short sample ranges (one GPU's share of
     // a k-space split, 4096 samples per coil at 256^2) then still fill the
@@ -1203,9 +1203,9 @@ hipError_t adj8_variant(const NudftTable& t, int nt, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Tiles of the split-form adjoint: (slice, 32 y, 128 x, sample split).
+// Tiles of the adjoint: (slice, 32 y, 128 x, sample split).
 int64_t adj8_tiles(const NudftItem& it) {
-    return (int64_t)it.nb * ceil_div(it.nx, kAdjCols8) * ceil_div(it.ny, kAdjRows) * it.ksplit;
+    return adj_tiles_per_split(it.nx, it.ny, it.nb) * it.ksplit;
 }
 
 }  // namespace

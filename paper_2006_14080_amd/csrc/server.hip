@@ -109,6 +109,7 @@ struct Server {
     int precision = MRI_FP32;
     int max_slots = 0;
     hipStream_t stream = nullptr;
+    bool own_stream = false;               // created here (the caller passed none)
     char* pool = nullptr;
     PoolAllocator* alloc = nullptr;
     SolveScalars* host_sc = nullptr;       // pinned readback of per-slot scalars
@@ -242,7 +243,7 @@ size_t mri_server_request_bytes(const mri_shape* shape, int precision) {
     return req_layout(*shape, precision, true).total;
 }
 
-int mri_server_create(size_t hbm_budget, int max_slots, int precision, void** srv) {
+int mri_server_create(size_t hbm_budget, int max_slots, int precision, void* stream, void** srv) {
     if (!srv || max_slots < 1 || max_slots > kMaxItems || hbm_budget < kWsAlign) return MRI_EINVAL;
     int rc = check_precision(precision);
     if (rc) return rc;
@@ -256,11 +257,15 @@ int mri_server_create(size_t hbm_budget, int max_slots, int precision, void** sr
         delete S;
         return MRI_ENOMEM;
     }
-    if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+    // The caller's stream if it gave one; the legacy default stream cannot be
+    // captured into a graph, so without one the server makes its own.
+    S->stream = static_cast<hipStream_t>(stream);
+    S->own_stream = S->stream == nullptr;
+    if ((S->own_stream && hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) ||
         hipHostMalloc(reinterpret_cast<void**>(&S->host_sc), sizeof(SolveScalars) * kMaxItems,
                       hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(S->pool);
-        if (S->stream) (void)hipStreamDestroy(S->stream);
+        if (S->own_stream && S->stream) (void)hipStreamDestroy(S->stream);
         delete S;
         return MRI_EHIP;
     }
@@ -420,7 +425,7 @@ int mri_server_destroy(void* srv) {
     if (S->graph) (void)hipGraphExecDestroy(S->graph);
     if (S->pool) (void)hipFree(S->pool);
     if (S->host_sc) (void)hipHostFree(S->host_sc);
-    if (S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->own_stream && S->stream) (void)hipStreamDestroy(S->stream);
     delete S->alloc;
     delete S;
     return MRI_OK;

@@ -19,7 +19,6 @@ struct SolveScalars {
     int32_t admm_iters;
     int32_t cg_steps;
     int32_t status;      // MRI_OK or MRI_ENUMERIC
-    uint32_t counter;    // unused (kept for layout)
     int32_t cg_it;       // CG steps taken in the current ADMM iteration
     int32_t pad;
 };

@@ -120,7 +120,6 @@ __global__ __launch_bounds__(kVecThreads) void k_solve_init(const SolveTable tab
         s.admm_iters = 0;
         s.cg_steps = 0;
         s.status = MRI_OK;
-        s.counter = 0u;
         s.cg_it = 0;
         s.pad = 0;
         if (it.admm_max <= 0) s.admm_active = 0;

@@ -56,8 +56,8 @@ class MriAdmmStats(ctypes.Structure):
 STATS_BYTES = ctypes.sizeof(MriAdmmStats)
 
 EXPORTS = ["nudft_forward", "nudft_adjoint", "nudft_adjoint_prepare", "nudft_adjoint_prepared",
-           "tv_forward", "tv_adjoint", "admm_solve", "mri_workspace_bytes", "mri_strerror",
-           "mri_last_hip_error"]
+           "tv_forward", "tv_adjoint", "admm_solve", "mri_workspace_bytes", "mri_adjoint_split",
+           "mri_strerror", "mri_last_hip_error"]
 
 _lib = None
 
@@ -89,6 +89,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.admm_solve.argtypes = [shp, vp, vp, vp, vp, prm, vp, vp, vp, sz, vp]
     lib.mri_workspace_bytes.argtypes = [shp, i32, prm]
     lib.mri_workspace_bytes.restype = sz
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.mri_adjoint_split.argtypes = [shp, i32p, i32p, i32p]
+    lib.mri_adjoint_split.restype = i32
     lib.mri_strerror.argtypes = [i32]
     lib.mri_strerror.restype = ctypes.c_char_p
     lib.mri_last_hip_error.argtypes = []
@@ -116,13 +119,42 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def _need(t: torch.Tensor, dtype, name: str):
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{name} must be a GPU tensor")
+def _need(t: torch.Tensor, dtype, name: str, shape=None):
+    """Check one tensor argument before any library call: type, dtype, exact
+    shape (when given) and contiguity.  A tensor that does not match the shape
+    the library is told about would make its kernels read or write outside
+    it, so every mismatch raises here and nothing is launched."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(int(v) for v in shape):
+        raise ValueError(f"{name} must have shape {tuple(int(v) for v in shape)}, got {tuple(t.shape)}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def _on_gpu(device=None, **tensors):
+    """Every tensor (None skipped) is a GPU tensor on one device (`device`
+    when given, else the first tensor's).  Called after the shape checks."""
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise TypeError(f"{name} must be a GPU tensor")
+        if device is None:
+            device = t.device
+        elif t.device != torch.device(device):
+            raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _check_inputs(sh: "MriShape", smaps: torch.Tensor, traj: torch.Tensor):
+    """smaps and traj against a shape: [nc, ny, nx] or [B, nc, ny, nx], and
+    [nk, 2] or [B, nk, 2] as its *_batched flags say."""
+    sm = (sh.ncoils, sh.ny, sh.nx)
+    tr = (sh.nk, 2)
+    _need(smaps, torch.complex64, "smaps", ((sh.batch,) + sm) if sh.smaps_batched else sm)
+    _need(traj, torch.float64, "traj", ((sh.batch,) + tr) if sh.traj_batched else tr)
 
 
 def make_shape(nx, ny, nc, nk, batch=1, traj_batched=False, smaps_batched=False) -> MriShape:
@@ -130,7 +162,15 @@ def make_shape(nx, ny, nc, nk, batch=1, traj_batched=False, smaps_batched=False)
 
 
 def shape_of(image_shape, smaps: torch.Tensor, traj: torch.Tensor) -> MriShape:
-    b, ny, nx = image_shape
+    """The MriShape of a [B, ny, nx] image with these coil maps and trajectory
+    (batched when they carry a leading slice axis)."""
+    if len(image_shape) != 3:
+        raise ValueError(f"image must be [B, ny, nx], got {tuple(image_shape)}")
+    b, ny, nx = (int(v) for v in image_shape)
+    if not isinstance(smaps, torch.Tensor) or not isinstance(traj, torch.Tensor):
+        raise TypeError("smaps and traj must be torch.Tensors")
+    if smaps.dim() not in (3, 4) or traj.dim() not in (2, 3):
+        raise ValueError("smaps must be [nc, ny, nx] or [B, nc, ny, nx]; traj [nk, 2] or [B, nk, 2]")
     smaps_batched = smaps.dim() == 4
     traj_batched = traj.dim() == 3
     nc = smaps.shape[-3]
@@ -152,6 +192,15 @@ def workspace_bytes(shape: MriShape, op: int, params: Optional[MriAdmmParams] = 
                                        ctypes.byref(params) if params is not None else None))
 
 
+def adjoint_split(shape: MriShape) -> dict:
+    """The adjoint's sample-range split for a shape: {'ksplit', 'kper',
+    'planes'} (partial images per slice)."""
+    ks, kp, pl = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().mri_adjoint_split(ctypes.byref(shape), ctypes.byref(ks), ctypes.byref(kp), ctypes.byref(pl)),
+           "mri_adjoint_split")
+    return {"ksplit": ks.value, "kper": kp.value, "planes": pl.value}
+
+
 def _workspace(shape, op, params=None, device=None):
     n = workspace_bytes(shape, op, params)
     if n == 0:
@@ -164,12 +213,13 @@ def nudft_forward(image: torch.Tensor, smaps: torch.Tensor, traj: torch.Tensor,
     """y = F(image), eq. (1): [B, ny, nx] -> [B, nc, nk]."""
     lib = load()
     _need(image, torch.complex64, "image")
-    _need(smaps, torch.complex64, "smaps")
-    _need(traj, torch.float64, "traj")
     sh = shape_of(image.shape, smaps, traj)
+    _check_inputs(sh, smaps, traj)
+    if out is not None:
+        _need(out, torch.complex64, "out", (sh.batch, sh.ncoils, sh.nk))
+    _on_gpu(image=image, smaps=smaps, traj=traj, out=out)
     if out is None:
         out = torch.empty((sh.batch, sh.ncoils, sh.nk), dtype=torch.complex64, device=image.device)
-    _need(out, torch.complex64, "out")
     ws, n = _workspace(sh, OP_FORWARD, device=image.device)
     _check(lib.nudft_forward(ctypes.byref(sh), _ptr(image), _ptr(smaps), _ptr(traj), _ptr(out),
                              precision, _ptr(ws), n, _stream()), "nudft_forward")
@@ -180,16 +230,17 @@ def nudft_adjoint(data: torch.Tensor, smaps: torch.Tensor, traj: torch.Tensor, n
                   precision: int = FP32, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """x = F^H(data): [B, nc, nk] -> [B, ny, nx]."""
     lib = load()
-    _need(data, torch.complex64, "data")
-    _need(smaps, torch.complex64, "smaps")
-    _need(traj, torch.float64, "traj")
+    if not isinstance(data, torch.Tensor) or data.dim() != 3:
+        raise ValueError("data must be a [B, nc, nk] tensor")
     b = data.shape[0]
     sh = shape_of((b, ny, nx), smaps, traj)
-    if tuple(data.shape) != (b, sh.ncoils, sh.nk):
-        raise ValueError("data must be [B, nc, nk]")
+    _need(data, torch.complex64, "data", (b, sh.ncoils, sh.nk))
+    _check_inputs(sh, smaps, traj)
+    if out is not None:
+        _need(out, torch.complex64, "out", (b, ny, nx))
+    _on_gpu(data=data, smaps=smaps, traj=traj, out=out)
     if out is None:
         out = torch.empty((b, ny, nx), dtype=torch.complex64, device=data.device)
-    _need(out, torch.complex64, "out")
     ws, n = _workspace(sh, OP_ADJOINT, device=data.device)
     _check(lib.nudft_adjoint(ctypes.byref(sh), _ptr(data), _ptr(smaps), _ptr(traj), _ptr(out),
                              precision, _ptr(ws), n, _stream()), "nudft_adjoint")
@@ -203,22 +254,22 @@ class AdjointPlan:
 
     def __init__(self, smaps: torch.Tensor, traj: torch.Tensor, ny: int, nx: int, batch: int = 1,
                  precision: int = FP32):
-        _need(smaps, torch.complex64, "smaps")
-        _need(traj, torch.float64, "traj")
         self.smaps, self.traj, self.precision = smaps, traj, precision
         self.shape = shape_of((batch, ny, nx), smaps, traj)
+        _check_inputs(self.shape, smaps, traj)
+        _on_gpu(smaps=smaps, traj=traj)
         self.ws, self.ws_bytes = _workspace(self.shape, OP_ADJOINT, device=smaps.device)
         _check(load().nudft_adjoint_prepare(ctypes.byref(self.shape), _ptr(traj), _ptr(self.ws),
                                             self.ws_bytes, _stream()), "nudft_adjoint_prepare")
 
     def __call__(self, data: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         sh = self.shape
-        _need(data, torch.complex64, "data")
-        if tuple(data.shape) != (sh.batch, sh.ncoils, sh.nk):
-            raise ValueError("data must be [B, nc, nk] of the plan's shape")
+        _need(data, torch.complex64, "data", (sh.batch, sh.ncoils, sh.nk))
+        if out is not None:
+            _need(out, torch.complex64, "out", (sh.batch, sh.ny, sh.nx))
+        _on_gpu(self.smaps.device, data=data, out=out)
         if out is None:
             out = torch.empty((sh.batch, sh.ny, sh.nx), dtype=torch.complex64, device=data.device)
-        _need(out, torch.complex64, "out")
         _check(load().nudft_adjoint_prepared(ctypes.byref(sh), _ptr(data), _ptr(self.smaps), _ptr(self.traj),
                                              _ptr(out), self.precision, _ptr(self.ws), self.ws_bytes,
                                              _stream()), "nudft_adjoint_prepared")
@@ -229,6 +280,9 @@ def tv_forward(image: torch.Tensor) -> torch.Tensor:
     """g = Theta(image): [B, ny, nx] -> [B, 2, ny, nx]."""
     lib = load()
     _need(image, torch.complex64, "image")
+    if image.dim() != 3:
+        raise ValueError(f"image must be [B, ny, nx], got {tuple(image.shape)}")
+    _on_gpu(image=image)
     b, ny, nx = image.shape
     sh = make_shape(nx, ny, 1, 1, b)
     g = torch.empty((b, 2, ny, nx), dtype=torch.complex64, device=image.device)
@@ -240,9 +294,10 @@ def tv_adjoint(grad: torch.Tensor) -> torch.Tensor:
     """x = Theta^H(grad): [B, 2, ny, nx] -> [B, ny, nx]."""
     lib = load()
     _need(grad, torch.complex64, "grad")
+    if grad.dim() != 4 or grad.shape[1] != 2:
+        raise ValueError(f"grad must be [B, 2, ny, nx], got {tuple(grad.shape)}")
+    _on_gpu(grad=grad)
     b, two, ny, nx = grad.shape
-    if two != 2:
-        raise ValueError("grad must be [B, 2, ny, nx]")
     sh = make_shape(nx, ny, 1, 1, b)
     x = torch.empty((b, ny, nx), dtype=torch.complex64, device=grad.device)
     _check(lib.tv_adjoint(ctypes.byref(sh), _ptr(grad), _ptr(x), _stream()), "tv_adjoint")
@@ -281,14 +336,17 @@ class AdmmSolver:
     def solve(self, smaps, traj, data, x0=None, out=None) -> torch.Tensor:
         lib = load()
         sh = self.shape
-        _need(smaps, torch.complex64, "smaps")
-        _need(traj, torch.float64, "traj")
-        _need(data, torch.complex64, "data")
+        dev = self.ws.device
+        img = (sh.batch, sh.ny, sh.nx)
+        _check_inputs(sh, smaps, traj)
+        _need(data, torch.complex64, "data", (sh.batch, sh.ncoils, sh.nk))
         if x0 is not None:
-            _need(x0, torch.complex64, "x0")
+            _need(x0, torch.complex64, "x0", img)
+        if out is not None:
+            _need(out, torch.complex64, "out", img)
+        _on_gpu(dev, smaps=smaps, traj=traj, data=data, x0=x0, out=out)
         if out is None:
-            out = torch.empty((sh.batch, sh.ny, sh.nx), dtype=torch.complex64, device=data.device)
-        _need(out, torch.complex64, "out")
+            out = torch.empty(img, dtype=torch.complex64, device=dev)
         _check(lib.admm_solve(ctypes.byref(sh), _ptr(smaps), _ptr(traj), _ptr(data), _ptr(x0),
                               ctypes.byref(self._cp), _ptr(out), _ptr(self.stats_buf),
                               _ptr(self.ws), self.ws_bytes, _stream()), "admm_solve")
@@ -307,7 +365,10 @@ class AdmmSolver:
 
 def admm_solve(smaps, traj, data, ny, nx, params: AdmmParams, x0=None):
     """One-shot ADMM-TV reconstruction (Alg. 4).  Returns (image, stats)."""
+    if not isinstance(data, torch.Tensor) or data.dim() != 3:
+        raise ValueError("data must be a [B, nc, nk] tensor")
     sh = shape_of((data.shape[0], ny, nx), smaps, traj)
+    _check_inputs(sh, smaps, traj)
     solver = AdmmSolver(sh, params, device=data.device)
     img = solver.solve(smaps, traj, data, x0)
     return img, solver.stats()

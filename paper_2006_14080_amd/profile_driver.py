@@ -14,8 +14,8 @@ The second runs admm_solve (2 ADMM x 5 CG, FP32) over SLICES slices of
 384x384 with one coil and 64 samples, so the NUDFT is negligible and the
 solver's memory-bound kernels work on multi-GB arrays (far beyond the 256 MB
 Infinity Cache), then copies 1 GiB three times (the plain-copy reference);
-it prints the pixel count and partial-image count that `profsum vecbw`
-needs.
+it prints the pixel count and the adjoint's partial-image count (from the
+library's mri_adjoint_split) that `profsum vecbw` reads.
 
 The third times (HIP events on the calling stream) nudft_forward and
 nudft_adjoint on one GPU's share of a k-space decomposition over 8 GPUs
@@ -55,9 +55,8 @@ def vector_sweep(slices: int):
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    # 64 samples are fewer than one sample split (512) and one coil is one
-    # coil group, so the adjoint writes a single partial image per slice.
-    print(f"profile driver done: npix={slices * n * n} coils={nc} planes=1", flush=True)
+    planes = mri.adjoint_split(shape)["planes"]
+    print(f"profile driver done: npix={slices * n * n} coils={nc} planes={planes}", flush=True)
 
 
 def _time_ms(fn, repeats: int) -> float:

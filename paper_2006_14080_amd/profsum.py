@@ -3,14 +3,17 @@
     python -m paper_2006_14080_amd.profsum stats <run_kernel_stats.csv> --cmd "<command>" [--top N]
     python -m paper_2006_14080_amd.profsum pmc <run_counter_collection.csv> --cmd "<command>"
     python -m paper_2006_14080_amd.profsum traffic <fetch.csv> <write.csv> --cmd "<command>" [--json out.json --key fp32]
-    python -m paper_2006_14080_amd.profsum vecbw <run_kernel_stats.csv> --cmd "<command>" --npix N --coils C --planes P
+    python -m paper_2006_14080_amd.profsum vecbw <run_kernel_stats.csv> <run log> --cmd "<command>" [--copy-bytes B]
     python -m paper_2006_14080_amd.profsum busy <run_kernel_trace.csv> --cmd "<command>"
     python -m paper_2006_14080_amd.profsum grid <run_kernel_trace.csv> --cmd "<command>"
 
 ``vecbw`` turns the durations of the solver's memory-bound kernels into
 achieved bandwidth from their algorithmic bytes per pixel (listed in
-VEC_BYTES; N = pixels of all slices, C = coils, P = adjoint partial images
-per slice), against the 8 TB/s HBM peak.
+VEC_BYTES), against the 8 TB/s HBM peak.  The pixel count (all slices), coil
+count and adjoint partial images per slice come from the run's own output
+(the line ``npix=N coils=C planes=P`` that the profile driver and the batch
+benchmark print, the plane count from the library's mri_adjoint_split), and
+a figure above the peak is an error: it means the byte count is wrong.
 
 ``grid`` lists the NUDFT kernels of a run per (kernel, grid size), so runs
 that launch one kernel at several shapes keep them apart.
@@ -115,6 +118,19 @@ VEC_BYTES = {
 HBM_PEAK = 8.0e12
 
 
+def run_sizes(log_path):
+    """(npix, coils, planes) from the last ``npix=N coils=C planes=P`` line of a run's output."""
+    import re
+    found = None
+    for line in open(log_path, errors="replace"):
+        m = re.search(r"npix=(\d+) coils=(\d+) planes=(\d+)", line)
+        if m:
+            found = tuple(int(v) for v in m.groups())
+    if found is None:
+        raise SystemExit(f"{log_path}: no 'npix=N coils=C planes=P' line (run the profile driver or the batch bench)")
+    return found
+
+
 def vecbw(path, npix, coils, planes, copy_bytes=None):
     rows = list(csv.DictReader(open(path)))
     out = [f"{'kernel':16s} {'calls':>6s} {'avg_us':>9s} {'bytes/px':>9s} {'GB/s':>8s} {'of 8 TB/s':>9s}"]
@@ -132,6 +148,9 @@ def vecbw(path, npix, coils, planes, copy_bytes=None):
         b = VEC_BYTES[k](coils, planes)
         us = float(r["AverageNs"]) / 1e3
         gbs = b * npix / (us * 1e-6) / 1e9
+        if gbs * 1e9 > HBM_PEAK:
+            raise SystemExit(f"{k}: {gbs:.0f} GB/s exceeds the HBM peak; its byte count "
+                             f"({b} B/px, {planes} planes) does not match the run")
         out.append(f"{k:16s} {int(r['Calls']):6d} {us:9.2f} {b:9d} {gbs:8.1f} {gbs * 1e9 / HBM_PEAK:9.1%}")
     return out
 
@@ -248,16 +267,15 @@ def main():
     ap.add_argument("--top", type=int, default=14)
     ap.add_argument("--json")
     ap.add_argument("--key")
-    ap.add_argument("--npix", type=int)
-    ap.add_argument("--coils", type=int)
-    ap.add_argument("--planes", type=int)
     ap.add_argument("--copy-bytes", type=int, help="vecbw: size of the reference device copy in the run")
     a = ap.parse_args()
     if a.mode == "vecbw":
+        npix, coils, planes = run_sizes(a.csv2)
         print("# solver memory-bound kernels: achieved bandwidth from algorithmic bytes")
         print(f"# command: {a.cmd}")
-        print(f"# pixels (all slices) = {a.npix}, coils = {a.coils}, adjoint partial images per slice = {a.planes}")
-        for line in vecbw(a.csv, a.npix, a.coils, a.planes, a.copy_bytes):
+        print(f"# pixels (all slices) = {npix}, coils = {coils}, adjoint partial images per slice = {planes} "
+              "(as printed by the run)")
+        for line in vecbw(a.csv, npix, coils, planes, a.copy_bytes):
             print(line)
         return 0
     if a.mode == "busy":

@@ -33,7 +33,7 @@ def _lib():
     lib = mri.load()
     if not getattr(lib, "_server_bound", False):
         vp = ctypes.c_void_p
-        lib.mri_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(vp)]
+        lib.mri_server_create.argtypes = [ctypes.c_size_t, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(vp)]
         lib.mri_server_submit.argtypes = [vp, ctypes.POINTER(MriRequest), ctypes.POINTER(ctypes.c_uint64)]
         lib.mri_server_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         lib.mri_server_poll.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(mri.MriAdmmStats),
@@ -56,20 +56,31 @@ def request_bytes(nx, ny, nc, nk, precision=mri.FP32) -> int:
 
 
 class Server:
-    """One device pool of `budget` bytes and up to `max_slots` concurrent solves."""
+    """One device pool of `budget` bytes and up to `max_slots` concurrent solves.
 
-    def __init__(self, budget: int, max_slots: int = 8, precision: int = mri.FP32):
+    `stream`: a torch.cuda.Stream (not the default stream) for all of the
+    server's device work, or None for a stream the server owns."""
+
+    def __init__(self, budget: int, max_slots: int = 8, precision: int = mri.FP32, stream=None):
         self.lib = _lib()
         self.precision = precision
         self.h = ctypes.c_void_p()
-        mri._check(self.lib.mri_server_create(int(budget), int(max_slots), int(precision), ctypes.byref(self.h)),
-                   "mri_server_create")
+        self.stream = stream          # kept alive as long as the server
+        sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p(0)
+        mri._check(self.lib.mri_server_create(int(budget), int(max_slots), int(precision), sp,
+                                              ctypes.byref(self.h)), "mri_server_create")
         self.shapes: Dict[int, tuple] = {}
 
     def submit(self, smaps: np.ndarray, traj: np.ndarray, data: np.ndarray, params: mri.AdmmParams,
                x0: Optional[np.ndarray] = None) -> int:
+        if smaps.ndim != 3 or traj.ndim != 2 or traj.shape[1] != 2:
+            raise ValueError("smaps must be [nc, ny, nx] and traj [nk, 2]")
         nc, ny, nx = smaps.shape
         nk = traj.shape[0]
+        if data.size != nc * nk:
+            raise ValueError(f"data must hold nc * nk = {nc * nk} samples, got {data.size}")
+        if x0 is not None and tuple(x0.shape) != (ny, nx):
+            raise ValueError(f"x0 must be [{ny}, {nx}], got {tuple(x0.shape)}")
         smaps = np.ascontiguousarray(smaps, np.complex64)
         traj = np.ascontiguousarray(traj, np.float64)
         data = np.ascontiguousarray(data, np.complex64).reshape(nc, nk)

@@ -214,12 +214,21 @@ def make_problem(wl: Workload, batch: Optional[int] = None) -> Problem:
     phantom seed + 1 offset by 1000 so no two draws share a stream.
     """
     nb = wl.batch if batch is None else batch
-    truth = np.stack([ellipse_phantom(wl.nx, wl.ny, wl.seed + b) for b in range(nb)])
+    truth = np.stack([slice_phantom(wl, b) for b in range(nb)])
     smaps = coil_maps(wl.nx, wl.ny, wl.nc)
     traj = radial_trajectory(wl.n_spokes, wl.n_readout)
-    noise = np.stack([complex_noise((wl.nc, wl.nk), wl.sigma, 1000 + wl.seed + b + 1)
-                      for b in range(nb)])
+    noise = np.stack([slice_noise(wl, b) for b in range(nb)])
     return Problem(wl, truth, smaps, traj, noise)
+
+
+def slice_phantom(wl: Workload, b: int) -> np.ndarray:
+    """Phantom of slice b of a workload (as in make_problem), [ny][nx]."""
+    return ellipse_phantom(wl.nx, wl.ny, wl.seed + b)
+
+
+def slice_noise(wl: Workload, b: int) -> np.ndarray:
+    """Noise of slice b of a workload (as in make_problem), complex128 [nc][nk]."""
+    return complex_noise((wl.nc, wl.nk), wl.sigma, 1000 + wl.seed + b + 1)
 
 
 @dataclasses.dataclass(frozen=True)

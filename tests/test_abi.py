@@ -46,6 +46,18 @@ def test_struct_layouts():
     assert ctypes.sizeof(mri.MriAdmmStats) == 32
 
 
+def test_adjoint_split(lib):
+    # 256^2 / 8 coils / 32768 samples: 16 ranges of 2048 samples, one coil
+    # group, so 16 partial images; 384^2 / 16 coils / 98304 samples: two coil
+    # groups of 8.
+    assert mri.adjoint_split(mri.make_shape(256, 256, 8, 32768)) == {"ksplit": 16, "kper": 2048, "planes": 16}
+    s384 = mri.adjoint_split(mri.make_shape(384, 384, 16, 98304, batch=32))
+    assert s384["planes"] == 2 * s384["ksplit"] and s384["ksplit"] * s384["kper"] >= 98304
+    # fewer samples than one range of 256: a single range
+    assert mri.adjoint_split(mri.make_shape(384, 384, 1, 64))["planes"] == 1
+    assert lib.mri_adjoint_split(ctypes.byref(mri.make_shape(0, 8, 1, 8)), None, None, None) == -1
+
+
 def test_strerror(lib):
     assert lib.mri_strerror(0) == b"success"
     assert b"invalid" in lib.mri_strerror(-1)

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 import torch
 
+import bars
 from oracle import admm as oadmm
 from oracle import nudft as onudft
 from paper_2006_14080_amd import mri, synth
@@ -42,12 +43,12 @@ def _oracle(p, data, b, lam, beta, na, nc, **kw):
     return oadmm.admm(data[b], p.smaps, p.traj, lam, beta, na, nc, **kw)
 
 
-# BF16x3 keeps ~16 bits per operand (per-operator error 3.8e-6); the solves
-# amplify operator errors 10-1000x (FP32's 2-6e-7 become 2-7e-5 at 30x5), so
-# its image lands between 2e-5 and 5e-3 depending on rounding details.  It is
-# held to 1e-3 on the 32x32 case and to 1e-2 at full size; FP32 and FP16x3
-# meet the 1e-4 bar everywhere.
-BAR = {mri.FP32: NRMSE, mri.FP16X3: NRMSE, mri.BF16X3: 1e-3}
+# BF16x3 keeps ~16 bits per operand (per-operator error ~4e-6).  The oracle's
+# own 10 x 3 solve at 32x32 moves its image by up to 2.9e-4 when its operators
+# carry that error (tests/golden/tolerances.json), so BF16x3 is held to twice
+# that there (tests/bars.py); FP32 and FP16x3 (operator errors <= 6e-7, image
+# shifts <= 7e-5) meet the 1e-4 bar.
+BAR = {mri.FP32: NRMSE, mri.FP16X3: NRMSE, mri.BF16X3: bars.BF16X3_ADMM32}
 
 
 @pytest.mark.parametrize("prec", [mri.FP32, mri.BF16X3, mri.FP16X3])
@@ -177,10 +178,50 @@ def test_admm256_full_counts_against_stored_oracle(prec):
 
 
 def test_admm256_full_counts_bf16x3_reported_error():
-    # The bf16 split keeps ~16 bits per operand (per-operator error ~4e-6);
-    # through 150 CG steps that gives an image NRMSE anywhere from 8e-5 to
-    # 3.4e-3 on this problem, depending on the rounding details of the build,
-    # so BF16x3 is not held to the 1e-4 bar that FP32 and FP16x3 meet here.
-    # Held to its measured range so a regression shows.
+    # Report only.  The bf16 split keeps ~16 bits per operand (per-operator
+    # error ~4e-6), and 150 CG steps amplify operator errors by two orders or
+    # more (at 32x32 and 30 CG steps the oracle's own image already moves by
+    # 70x its operator error), so which image BF16x3 reaches here depends on
+    # rounding order; no bar was derived for it (the oracle's 30 x 5 solve
+    # takes 12 minutes, too long to repeat under perturbation).  The value is
+    # printed; the only check is the paper's own accuracy figure for its
+    # bf16-based ADMM against an FP64 CPU (about 1 % relative difference,
+    # Sec. V), which a broken kernel would miss by orders of magnitude.
     e = _admm256_full(mri.BF16X3)
     assert e <= 1e-2
+
+
+GOLDEN_384 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "slices384_oracle.npz")
+
+
+@pytest.mark.parametrize("prec", [mri.FP32, mri.FP16X3, mri.BF16X3])
+def test_slices384_batch_solve_against_stored_oracle(prec):
+    # The 32-slice 384x384 batch (16 coils, 128 x 768 samples, lambda 5e-4) as
+    # one batched solve, so every operator is one grouped launch over all 32
+    # slices, at 2 ADMM x 2 CG.  Slices 0 and 31 solve the data stored with the
+    # oracle's reconstructions of them (tests/golden/make_slices384_golden.py);
+    # the other 30 take the GPU forward of their phantoms plus their noise.
+    # FP32 and FP16x3 within the 1e-4 bar; BF16x3 reported.
+    wl = synth.SLICES384
+    g = np.load(GOLDEN_384)
+    na, ncg = int(g["admm_iters"]), int(g["cg_iters"])
+    smaps = synth.coil_maps(wl.nx, wl.ny, wl.nc)
+    traj = synth.radial_trajectory(wl.n_spokes, wl.n_readout)
+    sm, tr = _gpu(smaps), _gpu(traj)
+    truth = _gpu(np.stack([synth.slice_phantom(wl, b) for b in range(wl.batch)]))
+    data = mri.nudft_forward(truth, sm, tr, precision=mri.FP32)
+    for b in range(wl.batch):
+        data[b] += _gpu(synth.slice_noise(wl, b).astype(np.complex64))
+    for i, b in enumerate(g["slices"]):
+        data[int(b)] = _gpu(g["data"][i])
+    img, st = mri.admm_solve(sm, tr, data, wl.ny, wl.nx,
+                             mri.AdmmParams(wl.lam, wl.beta, na, ncg, precision=prec))
+    img = img.cpu().numpy()
+    for i, b in enumerate(g["slices"]):
+        b = int(b)
+        assert st[b]["status"] == 0
+        assert (st[b]["admm_iters"], st[b]["cg_steps"]) == tuple(int(v) for v in g["counts"][i])
+        e = nrmse(img[b], g["images"][i])
+        print(f"{mri.PRECISION_NAMES[prec]}: 32x384^2 batch, slice {b}, {na}x{ncg}: image NRMSE vs stored "
+              f"oracle {e:.3e}")
+        assert e <= (NRMSE if prec != mri.BF16X3 else 1e-2)

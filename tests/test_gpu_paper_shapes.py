@@ -11,17 +11,24 @@
   steps) on the x8-undersampled set (13 spokes x 128 samples): the device's
   stopping decisions reproduce the oracle's iteration counts.  With lambda
   this small the 20-step CG solves an almost unregularised, ill-conditioned
-  least-squares problem whose iterates move by ~3.5e-3 (image NRMSE) under any
-  FP32-sized rounding: the oracle itself, with only its operator outputs
-  rounded to complex64, lands 3.2e-3 from its FP64 run, and relative operator
-  noise of 1e-7 .. 1e-6 gives 3.6e-3 .. 4.4e-3.  So the image is held to 1e-2
-  of the FP64 oracle here (not the 1e-4 of the benchmark settings, which
-  FP32 meets at 4.6e-5), and its error against the phantom must equal the
-  oracle's to 1 %.
+  least-squares problem whose iterates move by several 1e-3 (image NRMSE)
+  under any FP32-sized rounding: the oracle itself, with only its operator
+  outputs rounded to complex64 or carrying relative errors of 1e-7 .. 1e-6,
+  moves that far from its FP64 run (tests/golden/tolerances.json).  So the
+  image is held to twice the largest of those shifts (tests/bars.py), not
+  the 1e-4 of the benchmark settings, and its error against the phantom must
+  equal the oracle's to 1 %;
+* the large-image case of Sec. VI (1024 x 512, 12 coils, 101 x 1024 samples,
+  Table I settings) at 1 ADMM x 2 CG against a stored oracle reconstruction,
+  and the full Table I run against properties.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
+
+import bars
 
 from oracle import admm as oadmm
 from oracle import nudft as onudft
@@ -73,19 +80,45 @@ def test_table1_parameters_paper_shape(prec):
     e_truth, e_truth_ref = _rel(got, p.truth[0]), _rel(ref.image, p.truth[0])
     print(f"{mri.PRECISION_NAMES[prec]}: Table I run {ref.admm_iters} ADMM / {ref.cg_steps} CG, "
           f"image NRMSE vs oracle {e:.3e}, vs phantom {e_truth:.5f} (oracle {e_truth_ref:.5f})")
-    assert e <= 1e-2
+    assert e <= bars.TABLE1_128x64
     assert abs(e_truth - e_truth_ref) <= 0.01 * e_truth_ref
+
+
+GOLDEN_LARGE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table1_large_oracle.npz")
+
+
+@pytest.mark.parametrize("prec", [mri.FP32, mri.FP16X3, mri.BF16X3])
+def test_table1_large_image_reduced_counts_against_stored_oracle(prec):
+    # 1024x512 / 12 coils / 101x1024 samples with the Table I lambda, beta and
+    # tolerances at 1 ADMM x 2 CG, on the data stored with the oracle's own
+    # reconstruction (tests/golden/make_table1_large_golden.py): FP32 and
+    # FP16x3 within the 1e-4 bar, BF16x3 reported.
+    wl = synth.TABLE1_1024x512
+    g = np.load(GOLDEN_LARGE)
+    na, ncg = int(g["admm_max"]), int(g["cg_max"])
+    p = synth.make_problem(wl, batch=1)
+    img, st = mri.admm_solve(_gpu(p.smaps), _gpu(p.traj), _gpu(g["data"][None]), wl.ny, wl.nx,
+                             mri.AdmmParams(wl.lam, wl.beta, na, ncg, rtol=wl.rtol, atol=wl.atol, precision=prec))
+    assert st[0]["status"] == 0
+    assert st[0]["admm_iters"] == int(g["admm_iters"]) and st[0]["cg_steps"] == int(g["cg_steps"])
+    e = _rel(img.cpu().numpy()[0], g["image"])
+    print(f"{mri.PRECISION_NAMES[prec]}: 1024x512 Table I {na}x{ncg} image NRMSE vs stored oracle {e:.3e}")
+    if prec != mri.BF16X3:
+        assert e <= 1e-4
+    else:
+        assert e <= 1e-2     # report only; the paper's own ADMM accuracy figure (Sec. V) as a sanity check
 
 
 def test_table1_parameters_large_image():
     # The 1024x512 / 12-coil / 101x1024-sample problem of Sec. VI with the
-    # Table I settings.  Each operator here costs 5.2e12 flop, beyond what the
-    # FP64 oracle runs in test time, so the solve is held to properties that
-    # hold at any size: the device's stopping rules give valid counts and a
-    # CG-reduced data residual, and the two forms with FP32-level operators
-    # (FP32, FP16x3) reach the same image to the ill-conditioning bound shown
-    # against the oracle at 128x64 (1e-2), with the same error against the
-    # phantom to 1 %.  (Its operators are checked against the oracle on
+    # full Table I settings (up to 5 ADMM x 20 CG).  The oracle's run at these
+    # counts would take hours, so the solve is held to properties: the
+    # device's stopping rules give valid counts; the data residual
+    # ||F x - d|| / ||d|| falls well below that of the oracle's 1 x 2 run
+    # (stored golden) and under 1e-3 (measured 3.1e-4); and the two forms with
+    # FP32-level operators (FP32, FP16x3) reach the same image to the
+    # ill-conditioning bound derived at 128x64, with the same error against
+    # the phantom to 1 %.  (Its operators are checked against the oracle on
     # sampled outputs in test_gpu_shards.py.)
     wl = synth.TABLE1_1024x512
     p = synth.make_problem(wl)
@@ -105,8 +138,8 @@ def test_table1_parameters_large_image():
         e_truth = _rel(img.cpu().numpy()[0], p.truth[0])
         print(f"{mri.PRECISION_NAMES[prec]}: {s['admm_iters']} ADMM / {s['cg_steps']} CG, "
               f"data residual {resid:.4e}, NRMSE vs phantom {e_truth:.5f}")
-        assert resid <= 0.5
+        assert resid <= 1e-3 and resid < float(np.load(GOLDEN_LARGE)["resid"])
         out[prec] = (img.cpu().numpy()[0], e_truth)
     (a, ea), (b, eb) = out[mri.FP32], out[mri.FP16X3]
-    assert _rel(b, a) <= 1e-2
+    assert _rel(b, a) <= bars.TABLE1_128x64
     assert abs(ea - eb) <= 0.01 * ea

@@ -62,6 +62,18 @@ def test_mix_equals_alone_and_oracle(prec):
         assert np.linalg.norm(img - ref) / np.linalg.norm(ref) <= 1e-4
 
 
+def test_caller_stream():
+    # A server created on the caller's stream runs all its work there and
+    # gives the same result as one on a stream of its own.
+    a = _req(32, 24, 3, 8, 64, 31, na=3)
+    with serve.Server(1 << 28, max_slots=2) as srv:
+        ref = srv.run_until_idle([_submit(srv, *a)])
+    s = torch.cuda.Stream()
+    with serve.Server(1 << 28, max_slots=2, stream=s) as srv:
+        out = srv.run_until_idle([_submit(srv, *a)])
+    assert np.array_equal(list(ref.values())[0][0], list(out.values())[0][0])
+
+
 def test_staggered_arrivals_are_batch_invariant():
     # The same request run alone, then admitted while others are mid-solve.
     a = _req(32, 32, 4, 8, 64, 21, na=5)

@@ -153,10 +153,51 @@ def test_admm_reaches_minimiser_of_eq3():
     cp = _chambolle_pock(p, lam)
     oa, oc = _objective(p, res.image.ravel(), lam), _objective(p, cp, lam)
     assert abs(oa - oc) <= 1e-10 * oc
+    # The oracle's own eq. (3) agrees with the dense-matrix one and is minimal
+    # at the independent solver's point: moving it along random directions,
+    # either way, raises it (a wrong term would have a non-zero slope there).
+    o_star = admm.objective(cp.reshape(p.ny, p.nx), p.data, p.smaps, p.traj, lam)
+    assert abs(o_star - oc) <= 1e-10 * oc
+    for seed in range(6):
+        v = synth.random_complex((p.ny, p.nx), 300 + seed, np.complex128)
+        v *= 1e-4 * np.linalg.norm(cp) / np.linalg.norm(v)
+        for sgn in (1.0, -1.0):
+            o = admm.objective(cp.reshape(p.ny, p.nx) + sgn * v, p.data, p.smaps, p.traj, lam)
+            assert o >= o_star * (1.0 - 1e-12)
     np.testing.assert_allclose(res.image.ravel(), cp, atol=1e-9 * np.abs(cp).max())
     # the TV term is active: the minimiser differs from least squares
     ls = np.linalg.lstsq(p.F, p.data.ravel(), rcond=None)[0]
     assert np.abs(ls - cp).max() > 1e-2 * np.abs(cp).max()
+
+
+def test_objective_closed_form_single_pixel():
+    # Eq. (3) on an image with one non-zero pixel a and no data: every phase
+    # factor has unit modulus, so ||F x||^2 = nk |a|^2 sum_g |s_g(i, j)|^2, and
+    # the periodic differences of a single pixel are +-a at four places, so
+    # the TV term is 4 lam |a|.  |a| != 1 separates a squared TV term or an
+    # unsquared data term from the right one.
+    p = Tiny(nx=7, ny=5, nc=3, nk=30)
+    i, j, a, lam = 2, 3, 1.7 - 0.9j, 0.37
+    img = np.zeros((p.ny, p.nx), np.complex128)
+    img[i, j] = a
+    nk = p.traj.shape[0]
+    want = nk * abs(a) ** 2 * float(np.sum(np.abs(p.smaps[:, i, j].astype(np.complex128)) ** 2)) + lam * 4 * abs(a)
+    got = admm.objective(img, np.zeros_like(p.data), p.smaps, p.traj, lam)
+    assert abs(got - want) <= 1e-12 * want
+
+
+def test_objective_data_term_vanishes_on_consistent_data():
+    # d = F(x): the data term is zero and eq. (3) is lam times the l1 norm of
+    # the differences, here summed by hand over the image; F(0) = 0 leaves ||d||^2.
+    p = Tiny(nx=6, ny=4, nc=2, nk=24)
+    x = p.truth.astype(np.complex128) * (0.5 + 1.5j)
+    d = nudft.forward(x, p.smaps, p.traj)
+    l1 = sum(abs(x[r, (c + 1) % p.nx] - x[r, c]) + abs(x[(r + 1) % p.ny, c] - x[r, c])
+             for r in range(p.ny) for c in range(p.nx))
+    assert abs(admm.objective(x, d, p.smaps, p.traj, 0.3) - 0.3 * l1) <= 1e-9 * l1
+    zero = np.zeros((p.ny, p.nx), np.complex128)
+    dd = np.sum(np.abs(p.data) ** 2)
+    assert abs(admm.objective(zero, p.data, p.smaps, p.traj, 0.3) - dd) <= 1e-12 * dd
 
 
 def test_admm_scale_invariance():
