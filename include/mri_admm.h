@@ -107,6 +107,25 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
                   void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * nudft_forward_noalloc -- nudft_forward for callers that cannot allocate
+ * device memory or pass a workspace (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation).  The same kernels and
+ * results (bit for bit) as nudft_forward; the coil-weighted images go to a
+ * library-owned device scratch array of mri_noalloc_scratch_bytes() bytes
+ * (64 MiB, held on each GPU the library runs on until the process ends)
+ * instead of a workspace.  Nothing is allocated and nothing needs clearing:
+ * every scratch byte the kernels read is written earlier in the same call.
+ * All calls on one GPU share that GPU's array: calls that overlap on one GPU
+ * (different streams or threads without ordering) race and give undefined
+ * results.  The first call on a device looks up the array's address there.
+ * Errors: as nudft_forward; MRI_ENOMEM when the shape needs more than the
+ * scratch (mri_workspace_bytes(shape, MRI_OP_FORWARD, NULL) > 64 MiB).
+ */
+int nudft_forward_noalloc(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps,
+                          const double* traj, mri_c32* y, int precision, void* stream);
+size_t mri_noalloc_scratch_bytes(void);
+
+/*
  * nudft_adjoint -- x = F^H(y): the adjoint of eq. (1) with the conjugate coil
  * combine, which is the "inverse DFT" of Alg. 3 and the F^H of eq. (12)-(13):
  *   x[b][i][j] = sum_g conj(s[g][i][j]) sum_k exp(+i (w0_k x_j + w1_k y_i)) y[b][g][k].

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "plan.h"
@@ -38,6 +39,38 @@ NudftItem base_item(const mri_shape& s, const float2* smaps, const double* traj)
     it.smaps_bs = s.smaps_batched ? (int64_t)s.ncoils * s.nx * s.ny : 0;
     it.active_stride = 1;
     return it;
+}
+
+// Device scratch of nudft_forward_noalloc: the coil-weighted images live in
+// this file-scope array instead of a caller workspace.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Address of the current device's scratch array (nullptr on failure, with
+// the HIP error in *err).
+void* device_scratch(hipError_t* err) {
+    int dev = 0;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
 }
 
 NudftTable single_table(const NudftItem& it, int64_t ntiles) {
@@ -114,6 +147,21 @@ int nudft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps
     MRI_HIP(launch_nudft_forward(t, precision, s));
     return MRI_OK;
 }
+
+int nudft_forward_noalloc(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps, const double* traj,
+                          mri_c32* y, int precision, void* stream) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if ((rc = check_precision(precision))) return rc;
+    if (!x || !smaps || !traj || !y) return MRI_EINVAL;
+    if (forward_ws(*shape) > kNoallocScratchBytes) return MRI_ENOMEM;
+    hipError_t e = hipSuccess;
+    void* ws = device_scratch(&e);
+    if (!ws) return hip_fail(e);
+    return nudft_forward(shape, x, smaps, traj, y, precision, ws, kNoallocScratchBytes, stream);
+}
+
+size_t mri_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
 
 int nudft_adjoint_prepare(const mri_shape* shape, const double* traj, void* ws, size_t ws_bytes, void* stream) {
     int rc = check_shape(shape);

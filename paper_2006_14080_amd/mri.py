@@ -55,7 +55,7 @@ class MriAdmmStats(ctypes.Structure):
 
 STATS_BYTES = ctypes.sizeof(MriAdmmStats)
 
-EXPORTS = ["nudft_forward", "nudft_adjoint", "nudft_adjoint_prepare", "nudft_adjoint_prepared",
+EXPORTS = ["nudft_forward", "nudft_forward_noalloc", "mri_noalloc_scratch_bytes", "nudft_adjoint", "nudft_adjoint_prepare", "nudft_adjoint_prepared",
            "tv_forward", "tv_adjoint", "admm_solve", "mri_workspace_bytes", "mri_adjoint_split",
            "mri_strerror", "mri_last_hip_error"]
 
@@ -82,6 +82,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     prm = ctypes.POINTER(MriAdmmParams)
     lib.nudft_forward.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.nudft_adjoint.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
+    lib.nudft_forward_noalloc.argtypes = [shp, vp, vp, vp, vp, i32, vp]
+    lib.nudft_forward_noalloc.restype = i32
+    lib.mri_noalloc_scratch_bytes.argtypes = []
+    lib.mri_noalloc_scratch_bytes.restype = sz
     lib.nudft_adjoint_prepare.argtypes = [shp, vp, vp, sz, vp]
     lib.nudft_adjoint_prepared.argtypes = [shp, vp, vp, vp, vp, i32, vp, sz, vp]
     lib.tv_forward.argtypes = [shp, vp, vp, vp]
@@ -223,6 +227,25 @@ def nudft_forward(image: torch.Tensor, smaps: torch.Tensor, traj: torch.Tensor,
     ws, n = _workspace(sh, OP_FORWARD, device=image.device)
     _check(lib.nudft_forward(ctypes.byref(sh), _ptr(image), _ptr(smaps), _ptr(traj), _ptr(out),
                              precision, _ptr(ws), n, _stream()), "nudft_forward")
+    return out
+
+
+def nudft_forward_noalloc(image: torch.Tensor, smaps: torch.Tensor, traj: torch.Tensor,
+                          precision: int = FP32, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """nudft_forward without a workspace: the library's static device scratch
+    (mri_noalloc_scratch_bytes) holds the coil-weighted images.  Calls that
+    overlap on one GPU race for that scratch."""
+    lib = load()
+    _need(image, torch.complex64, "image")
+    sh = shape_of(image.shape, smaps, traj)
+    _check_inputs(sh, smaps, traj)
+    if out is not None:
+        _need(out, torch.complex64, "out", (sh.batch, sh.ncoils, sh.nk))
+    _on_gpu(image=image, smaps=smaps, traj=traj, out=out)
+    if out is None:
+        out = torch.empty((sh.batch, sh.ncoils, sh.nk), dtype=torch.complex64, device=image.device)
+    _check(lib.nudft_forward_noalloc(ctypes.byref(sh), _ptr(image), _ptr(smaps), _ptr(traj), _ptr(out),
+                                     precision, _stream()), "nudft_forward_noalloc")
     return out
 
 
