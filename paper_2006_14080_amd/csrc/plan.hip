@@ -71,7 +71,7 @@ AdmmLayout admm_layout(const mri_shape& s, int precision) {
     const size_t vec = ws_align(sizeof(float2) * npix * s.batch);
     adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, precision, &L.ksplit, &L.kper);
     L.nplanes = adj_partial_planes(s.ncoils, L.ksplit);
-    L.nblk = (int32_t)ceil_div(npix, kVecBlockPix);
+    L.nblk = (int32_t)vec_tiles(s.nx, s.ny);
     size_t o = 0;
     L.rho = o;  o += vec;
     L.rho0 = o; o += vec;

@@ -25,7 +25,7 @@ struct SolveScalars {
 
 // One solve (nb slices of one shape) as seen by the vector kernels.
 struct SolveItem {
-    int32_t nx, ny, nb, nblk;       // nblk: vector blocks per slice
+    int32_t nx, ny, nb, nblk;       // nblk: vector blocks (tiles) per slice
     int32_t block_begin;            // first block of this item in a grouped launch
     int32_t ksplit;                 // partial images per slice from the adjoint
     int64_t npix;
@@ -52,9 +52,15 @@ struct SolveTable {
     SolveItem it[kMaxItems];
 };
 
+// Vector-kernel tiles: a block of kVecThreads threads covers kTileX columns x
+// kTileY rows of one slice; each thread one column and kVecRows rows.
 constexpr int kVecThreads = 256;
-constexpr int kVecPix = 4;                                // pixels per thread
-constexpr int kVecBlockPix = kVecThreads * kVecPix;       // pixels per block
+constexpr int kTileX = 64;
+constexpr int kVecRows = 4;
+constexpr int kTileY = (kVecThreads / kTileX) * kVecRows;   // 16
+__host__ __device__ inline int vec_tiles(int nx, int ny) {
+    return ((nx + kTileX - 1) / kTileX) * ((ny + kTileY - 1) / kTileY);
+}
 
 enum FinishMode { kFinishFhd = 0, kFinishCgInit = 1, kFinishCgStep = 2 };
 enum FinalizeMode { kFinCgInit = 0, kFinCgStep = 1, kFinCgUpdate = 2, kFinDual = 3 };

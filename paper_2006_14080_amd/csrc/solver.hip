@@ -3,9 +3,17 @@
 // right-hand side, the CG updates, the dual update, and the reduction that
 // finishes each application of the normal matrix A = F^H F + (beta/2) Theta^H Theta.
 //
-// All are memory-bound: each thread takes kVecPix pixels kVecThreads apart
-// (coalesced along x), issuing the loads of all of them before any store so
-// a wave keeps several requests in flight per array.  Vector
+// All are memory-bound.  A block covers a tile of 64 columns x 16 rows of one
+// slice; each thread owns one column and four consecutive rows, so a wave
+// reads 64 consecutive pixels of a row (coalesced) and the stencils of Theta,
+// Theta^H and Theta^H Theta get their vertical neighbours from rows the
+// thread loads anyway (six rows for four outputs of the 5-point stencil) and
+// their horizontal neighbours from the adjacent lanes (wave shuffles), with
+// real loads only where a neighbour lies outside the wave's 64 columns or
+// wraps around.  Every thread issues all its loads before any store.  Arrays
+// a kernel touches once per pixel are read and written with non-temporal
+// (streaming) accesses; arrays a stencil reads at neighbouring pixels use
+// ordinary loads, so their lines stay in cache for the neighbours.  Vector
 // arithmetic is FP32; inner products and norms accumulate in FP64 and are
 // summed in a fixed order: wave shuffles, waves in index order, per-block
 // partials written to memory, then one finalize block per slice (k_finalize)
@@ -18,43 +26,83 @@
 namespace mri {
 namespace {
 
-struct Loc {
+// The tile of one block and this thread's place in it: column x, rows
+// y0 .. y0 + kVecRows - 1 (those below ny, in a column below nx, are outputs).
+struct Tile {
     int item, b, blk;
-    int pix0;           // first pixel of this thread; its others follow every kVecThreads
+    int lane, x, y0;
+    bool xok;
 };
 
-// Blocks are remapped so each XCD works on one contiguous pixel range: the
-// stencils' neighbouring rows are then in that XCD's own L2.
-__device__ __forceinline__ Loc locate(const SolveTable& t) {
+// Blocks are remapped so each XCD works on one contiguous band of rows: the
+// stencils' neighbouring rows are then in that XCD's own L2.  Tiles are
+// numbered column-tile fastest within a slice.
+__device__ __forceinline__ Tile locate(const SolveTable& t) {
     const int g = xcd_remap(blockIdx.x, t.total_blocks);
     int i = 0;
     while (i + 1 < t.nitems && g >= t.it[i + 1].block_begin) ++i;
     const SolveItem& it = t.it[i];
     const int local = g - it.block_begin;
-    Loc l;
+    Tile l;
     l.item = i;
     l.b = local / it.nblk;
     l.blk = local % it.nblk;
-    l.pix0 = l.blk * kVecBlockPix + (int)threadIdx.x;
+    const int ntx = (it.nx + kTileX - 1) / kTileX;
+    const int tx = l.blk % ntx, ty = l.blk / ntx;
+    l.lane = threadIdx.x % kTileX;
+    l.x = tx * kTileX + l.lane;
+    l.y0 = ty * kTileY + (threadIdx.x / kTileX) * kVecRows;
+    l.xok = l.x < it.nx;
     return l;
 }
 
-__device__ __forceinline__ int pix_of(const Loc& l, int j) { return l.pix0 + j * kVecThreads; }
+// Row y0 + i of the thread's band for loads: rows past the image wrap to row
+// 0 just past the end (the periodic neighbour of the last row) and otherwise
+// clamp to the last row (their values are never used).
+__device__ __forceinline__ int load_row(const Tile& l, int i, int ny) {
+    const int r = l.y0 + i;
+    return r < ny ? r : (r == ny ? 0 : ny - 1);
+}
+// The row above y0 (periodic), clamped like load_row.
+__device__ __forceinline__ int row_above(const Tile& l, int ny) {
+    return l.y0 == 0 ? ny - 1 : min(l.y0 - 1, ny - 1);
+}
+__device__ __forceinline__ bool row_ok(const Tile& l, int i, int ny) { return l.xok && l.y0 + i < ny; }
 
-// Periodic neighbours of pixel p in an ny x nx image.
-struct Nb {
-    int64_t xp, xm, yp, ym;   // (i, j+1), (i, j-1), (i+1, j), (i-1, j)
-};
-__device__ __forceinline__ Nb neighbours(int p, int nx, int ny) {
-    const int i = p / nx, j = p - i * nx;
-    const int jp = j + 1 == nx ? 0 : j + 1, jm = j == 0 ? nx - 1 : j - 1;
-    const int ip = i + 1 == ny ? 0 : i + 1, im = i == 0 ? ny - 1 : i - 1;
-    Nb n;
-    n.xp = (int64_t)i * nx + jp;
-    n.xm = (int64_t)i * nx + jm;
-    n.yp = (int64_t)ip * nx + j;
-    n.ym = (int64_t)im * nx + j;
-    return n;
+// Streaming (non-temporal) complex loads and stores.
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+    const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(float2* p, float2 v) {
+    __builtin_nontemporal_store(f2v{v.x, v.y}, reinterpret_cast<f2v*>(p));
+}
+
+// Horizontal periodic neighbours.  The lanes of a wave hold 64 adjacent
+// columns of a row, so a value's left and right neighbours come from the
+// adjacent lanes (wave shuffles); only the first lane (left) and the last
+// lane or the image's last column (right) load theirs.  The edge loads are
+// issued with the thread's other loads (edge_left / edge_right, before any
+// use), so a wave makes one memory round trip; left_of / right_of then pick
+// the shuffled or the loaded value and must be called by every lane.
+__device__ __forceinline__ float2 edge_left(const float2* a, int row, int nx, const Tile& l) {
+    float2 v = make_float2(0.f, 0.f);
+    if (l.lane == 0) v = a[(int64_t)row * nx + (l.x == 0 ? nx - 1 : l.x - 1)];   // lane 0 always has x < nx
+    return v;
+}
+__device__ __forceinline__ float2 edge_right(const float2* a, int row, int nx, const Tile& l) {
+    float2 v = make_float2(0.f, 0.f);
+    if (l.lane == kTileX - 1 || l.x + 1 >= nx) v = a[(int64_t)row * nx + (l.x + 1 >= nx ? 0 : l.x + 1)];
+    return v;
+}
+__device__ __forceinline__ float2 left_of(const Tile& l, float2 c, float2 edge) {
+    const float2 v = make_float2(__shfl_up(c.x, 1, 64), __shfl_up(c.y, 1, 64));
+    return l.lane == 0 ? edge : v;
+}
+__device__ __forceinline__ float2 right_of(const Tile& l, int nx, float2 c, float2 edge) {
+    const float2 v = make_float2(__shfl_down(c.x, 1, 64), __shfl_down(c.y, 1, 64));
+    return (l.lane == kTileX - 1 || l.x + 1 >= nx) ? edge : v;
 }
 
 __device__ __forceinline__ double cnorm2(float2 a) {
@@ -96,20 +144,18 @@ __device__ __forceinline__ void fail_numeric(SolveScalars& s) {
 
 // ---- initialisation: rho = x0 (or 0), eta = 0, scalars reset ---------------
 __global__ __launch_bounds__(kVecThreads) void k_solve_init(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
-    const int npix = (int)it.npix;
+    const int64_t base = (int64_t)l.b * it.npix, ebase = 2 * base;
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = pix_of(l, j);
-        if (pix >= npix) break;
-        const int64_t o = (int64_t)l.b * it.npix + pix;
-        const float2 v = it.x0 ? it.x0[o] : make_float2(0.f, 0.f);
-        it.rho[o] = v;
-        it.rho0[o] = v;
-        const int64_t e = (int64_t)l.b * 2 * it.npix + pix;
-        it.eta[e] = make_float2(0.f, 0.f);
-        it.eta[e + it.npix] = make_float2(0.f, 0.f);
+    for (int j = 0; j < kVecRows; ++j) {
+        if (!row_ok(l, j, it.ny)) break;
+        const int64_t pix = (int64_t)(l.y0 + j) * it.nx + l.x;
+        const float2 v = it.x0 ? it.x0[base + pix] : make_float2(0.f, 0.f);
+        st_nt(it.rho + base + pix, v);
+        st_nt(it.rho0 + base + pix, v);
+        st_nt(it.eta + ebase + pix, make_float2(0.f, 0.f));
+        st_nt(it.eta + ebase + it.npix + pix, make_float2(0.f, 0.f));
     }
     if (l.blk == 0 && threadIdx.x == 0) {
         SolveScalars& s = it.sc[l.b];
@@ -127,65 +173,87 @@ __global__ __launch_bounds__(kVecThreads) void k_solve_init(const SolveTable tab
 }
 
 // ---- eq. (9)-(10): mu = S_{lambda/beta}(Theta rho + eta) ---------------------
+// Theta rho at (y, x) = (rho(y, x+1) - rho(y, x), rho(y+1, x) - rho(y, x)).
 __global__ __launch_bounds__(kVecThreads) void k_mu(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     if (!it.sc[l.b].admm_active) return;
-    const int npix = (int)it.npix;
+    const int nx = it.nx, ny = it.ny;
+    const int xc = min(l.x, nx - 1);
     const float2* rho = it.rho + (int64_t)l.b * it.npix;
     const float2* eta = it.eta + (int64_t)l.b * 2 * it.npix;
     float2* mu = it.mu + (int64_t)l.b * 2 * it.npix;
-    float2 z0[kVecPix], z1[kVecPix];
+    float2 r[kVecRows + 1], e0[kVecRows], e1[kVecRows], er[kVecRows];
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = min(pix_of(l, j), npix - 1);
-        const Nb n = neighbours(pix, it.nx, it.ny);
-        const float2 r0 = rho[pix];
-        z0[j] = cadd(csub(rho[n.xp], r0), eta[pix]);
-        z1[j] = cadd(csub(rho[n.yp], r0), eta[pix + it.npix]);
+    for (int j = 0; j < kVecRows; ++j) er[j] = edge_right(rho, load_row(l, j, ny), nx, l);
+#pragma unroll
+    for (int i = 0; i <= kVecRows; ++i) r[i] = rho[(int64_t)load_row(l, i, ny) * nx + xc];
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) {
+        const int64_t pix = (int64_t)load_row(l, j, ny) * nx + xc;
+        e0[j] = ld_nt(eta + pix);
+        e1[j] = ld_nt(eta + it.npix + pix);
     }
+    float2 rr[kVecRows];
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = pix_of(l, j);
-        if (pix >= npix) break;
-        const float2 z[2] = {z0[j], z1[j]};
+    for (int j = 0; j < kVecRows; ++j) rr[j] = right_of(l, nx, r[j], er[j]);
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) {
+        if (!row_ok(l, j, ny)) break;
+        const int64_t pix = (int64_t)(l.y0 + j) * nx + l.x;
+        const float2 z[2] = {cadd(csub(rr[j], r[j]), e0[j]), cadd(csub(r[j + 1], r[j]), e1[j])};
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const float mag = sqrtf(z[c].x * z[c].x + z[c].y * z[c].y);
             const float sc = mag > it.thr ? 1.0f - it.thr / mag : 0.0f;
-            mu[pix + c * it.npix] = cscale(z[c], sc);
+            st_nt(mu + c * it.npix + pix, cscale(z[c], sc));
         }
     }
 }
 
 // ---- eq. (13): b = F^H d + (beta/2) Theta^H (mu - eta) -----------------------
+// Theta^H g at (y, x) = g0(y, x-1) - g0(y, x) + g1(y-1, x) - g1(y, x), g = mu - eta.
 __global__ __launch_bounds__(kVecThreads) void k_rhs(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     if (!it.sc[l.b].admm_active) return;
-    const int npix = (int)it.npix;
+    const int nx = it.nx, ny = it.ny;
+    const int xc = min(l.x, nx - 1);
     const int64_t e = (int64_t)l.b * 2 * it.npix;
     const float2* mu0 = it.mu + e;
     const float2* mu1 = mu0 + it.npix;
     const float2* et0 = it.eta + e;
     const float2* et1 = et0 + it.npix;
     const int64_t base = (int64_t)l.b * it.npix;
-    float2 out[kVecPix];
+    // g1 on the row above the band and the band's rows; g0 on the band's rows
+    float2 g1[kVecRows + 1], g0[kVecRows], fh[kVecRows], el[kVecRows];
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int p = min(pix_of(l, j), npix - 1);
-        const Nb n = neighbours(p, it.nx, it.ny);
-        // Theta^H g = g0(i, j-1) - g0(i, j) + g1(i-1, j) - g1(i, j), g = mu - eta
-        const float2 g0m = csub(mu0[n.xm], et0[n.xm]), g0 = csub(mu0[p], et0[p]);
-        const float2 g1m = csub(mu1[n.ym], et1[n.ym]), g1 = csub(mu1[p], et1[p]);
-        const float2 th = cadd(csub(g0m, g0), csub(g1m, g1));
-        out[j] = cadd(it.fhd[base + p], cscale(th, it.half_beta));
+    for (int j = 0; j < kVecRows; ++j) {      // g0 at x - 1 for lane 0
+        el[j] = make_float2(0.f, 0.f);
+        if (l.lane == 0) {
+            const int64_t o = (int64_t)load_row(l, j, ny) * nx + (l.x == 0 ? nx - 1 : l.x - 1);
+            el[j] = csub(mu0[o], et0[o]);
+        }
+    }
+    {
+        const int64_t pa = (int64_t)row_above(l, ny) * nx + xc;
+        g1[0] = csub(mu1[pa], et1[pa]);
     }
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int p = pix_of(l, j);
-        if (p >= npix) break;
-        it.b[base + p] = out[j];
+    for (int j = 0; j < kVecRows; ++j) {
+        const int64_t pix = (int64_t)load_row(l, j, ny) * nx + xc;
+        g1[j + 1] = csub(mu1[pix], et1[pix]);
+        g0[j] = csub(mu0[pix], et0[pix]);
+        fh[j] = ld_nt(it.fhd + base + pix);
+    }
+    float2 gl[kVecRows];
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) gl[j] = left_of(l, g0[j], el[j]);
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) {
+        if (!row_ok(l, j, ny)) break;
+        const float2 th = cadd(csub(gl[j], g0[j]), csub(g1[j], g1[j + 1]));
+        st_nt(it.b + base + (int64_t)(l.y0 + j) * nx + l.x, cadd(fh[j], cscale(th, it.half_beta)));
     }
 }
 
@@ -197,7 +265,7 @@ __global__ __launch_bounds__(kVecThreads) void k_rhs(const SolveTable tab) {
 // periodic 5-point stencil 4 v - (four neighbours).
 template <int mode>
 __global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     SolveScalars& sc = it.sc[l.b];
     if constexpr (mode == kFinishCgInit) {
@@ -206,60 +274,78 @@ __global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab
     if constexpr (mode == kFinishCgStep) {
         if (!sc.cg_active) return;
     }
-    const int npix = (int)it.npix;
+    const int nx = it.nx, ny = it.ny;
+    const int xc = min(l.x, nx - 1);
     const int64_t base = (int64_t)l.b * it.npix;
     const int64_t stride = (int64_t)it.nb * it.npix;
-    // Partial images in plane order (FP64), all pixels of the thread at once.
-    double sr[kVecPix], si[kVecPix];
-    int pc[kVecPix];
+    int64_t pc[kVecRows];
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        pc[j] = min(pix_of(l, j), npix - 1);
-        sr[j] = si[j] = 0.0;
+    for (int j = 0; j < kVecRows; ++j) pc[j] = (int64_t)load_row(l, j, ny) * nx + xc;
+    // The stencil's and the CG start's operands first (rows above, within and
+    // below the band, edge columns, b), then the partial images.
+    const float2* src = mode == kFinishCgStep ? it.p + base : (it.warm ? it.rho + base : it.rho0 + base);
+    float2 c[kVecRows + 2], el[kVecRows], er[kVecRows], bv[kVecRows];
+    if constexpr (mode != kFinishFhd) {
+#pragma unroll
+        for (int j = 0; j < kVecRows; ++j) {
+            el[j] = edge_left(src, load_row(l, j, ny), nx, l);
+            er[j] = edge_right(src, load_row(l, j, ny), nx, l);
+        }
+        c[0] = src[(int64_t)row_above(l, ny) * nx + xc];
+#pragma unroll
+        for (int i = 0; i <= kVecRows; ++i) c[i + 1] = src[(int64_t)load_row(l, i, ny) * nx + xc];
+        if constexpr (mode == kFinishCgInit) {
+#pragma unroll
+            for (int j = 0; j < kVecRows; ++j) bv[j] = ld_nt(it.b + base + pc[j]);
+        }
     }
+    // Partial images in plane order (FP64).
+    double sr[kVecRows], si[kVecRows];
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) sr[j] = si[j] = 0.0;
     const float2* pp = it.part + base;
+#pragma unroll 2
     for (int s = 0; s < it.ksplit; ++s) {
-        float2 v[kVecPix];
+        float2 v[kVecRows];
 #pragma unroll
-        for (int j = 0; j < kVecPix; ++j) v[j] = pp[s * stride + pc[j]];
+        for (int j = 0; j < kVecRows; ++j) v[j] = ld_nt(pp + s * stride + pc[j]);
 #pragma unroll
-        for (int j = 0; j < kVecPix; ++j) {
+        for (int j = 0; j < kVecRows; ++j) {
             sr[j] += v[j].x;
             si[j] += v[j].y;
         }
     }
-    double v0 = 0.0;
     if constexpr (mode == kFinishFhd) {
 #pragma unroll
-        for (int j = 0; j < kVecPix; ++j)
-            if (pix_of(l, j) < npix) it.fhd[base + pc[j]] = make_float2((float)sr[j], (float)si[j]);
+        for (int j = 0; j < kVecRows; ++j)
+            if (row_ok(l, j, ny)) st_nt(it.fhd + base + pc[j], make_float2((float)sr[j], (float)si[j]));
     } else {
-        const float2* src = mode == kFinishCgStep ? it.p + base : (it.warm ? it.rho + base : it.rho0 + base);
-        float2 q[kVecPix], c[kVecPix], bv[kVecPix];
+        float2 q[kVecRows];
 #pragma unroll
-        for (int j = 0; j < kVecPix; ++j) {
-            const Nb n = neighbours(pc[j], it.nx, it.ny);
-            c[j] = src[pc[j]];
-            float2 lap = cscale(c[j], 4.0f);
-            lap = csub(lap, src[n.xp]);
-            lap = csub(lap, src[n.xm]);
-            lap = csub(lap, src[n.yp]);
-            lap = csub(lap, src[n.ym]);
+        for (int j = 0; j < kVecRows; ++j) {
+            const float2 lft = left_of(l, c[j + 1], el[j]);
+            const float2 rgt = right_of(l, nx, c[j + 1], er[j]);
+            float2 lap = cscale(c[j + 1], 4.0f);
+            lap = csub(lap, rgt);
+            lap = csub(lap, lft);
+            lap = csub(lap, c[j + 2]);
+            lap = csub(lap, c[j]);
             q[j] = cadd(make_float2((float)sr[j], (float)si[j]), cscale(lap, it.half_beta));
-            if constexpr (mode == kFinishCgInit) bv[j] = it.b[base + pc[j]];
         }
+        double v0 = 0.0;
 #pragma unroll
-        for (int j = 0; j < kVecPix; ++j) {
-            if (pix_of(l, j) >= npix) break;
+        for (int j = 0; j < kVecRows; ++j) {
+            if (!row_ok(l, j, ny)) break;
             const int64_t o = base + pc[j];
+            const float2 cj = c[j + 1];
             if constexpr (mode == kFinishCgStep) {
-                it.q[o] = q[j];
-                v0 += (double)c[j].x * q[j].x + (double)c[j].y * q[j].y;
+                st_nt(it.q + o, q[j]);
+                v0 += (double)cj.x * q[j].x + (double)cj.y * q[j].y;
             } else {
                 const float2 r = csub(bv[j], q[j]);
-                it.r[o] = r;
-                it.p[o] = r;
-                it.xnew[o] = c[j];
+                st_nt(it.r + o, r);
+                st_nt(it.p + o, r);
+                st_nt(it.xnew + o, cj);
                 v0 += cnorm2(r);
             }
         }
@@ -269,30 +355,31 @@ __global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab
 
 // ---- Alg. 2 step: x += alpha d; r -= alpha A d; tau' = r^H r ------------------
 __global__ __launch_bounds__(kVecThreads) void k_cg_update(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     const SolveScalars& sc = it.sc[l.b];
     if (!sc.cg_active) return;
     const float a = (float)sc.alpha_cg;
-    const int npix = (int)it.npix;
+    const int nx = it.nx, ny = it.ny;
+    const int xc = min(l.x, nx - 1);
     const int64_t base = (int64_t)l.b * it.npix;
-    float2 x[kVecPix], r[kVecPix];
+    float2 x[kVecRows], r[kVecRows];
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int64_t o = base + min(pix_of(l, j), npix - 1);
-        const float2 p = it.p[o], q = it.q[o];
-        x[j] = it.xnew[o];
-        r[j] = it.r[o];
+    for (int j = 0; j < kVecRows; ++j) {
+        const int64_t o = base + (int64_t)load_row(l, j, ny) * nx + xc;
+        const float2 p = ld_nt(it.p + o), q = ld_nt(it.q + o);
+        x[j] = ld_nt(it.xnew + o);
+        r[j] = ld_nt(it.r + o);
         x[j] = make_float2(fmaf(a, p.x, x[j].x), fmaf(a, p.y, x[j].y));
         r[j] = make_float2(fmaf(-a, q.x, r[j].x), fmaf(-a, q.y, r[j].y));
     }
     double v0 = 0.0;
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = pix_of(l, j);
-        if (pix >= npix) break;
-        it.xnew[base + pix] = x[j];
-        it.r[base + pix] = r[j];
+    for (int j = 0; j < kVecRows; ++j) {
+        if (!row_ok(l, j, ny)) break;
+        const int64_t o = base + (int64_t)(l.y0 + j) * nx + l.x;
+        st_nt(it.xnew + o, x[j]);
+        st_nt(it.r + o, r[j]);
         v0 += cnorm2(r[j]);
     }
     block_partials(v0, 0.0, it, l.b, l.blk);
@@ -300,59 +387,66 @@ __global__ __launch_bounds__(kVecThreads) void k_cg_update(const SolveTable tab)
 
 // ---- Alg. 2 direction: d = r + (tau'/tau) d -----------------------------------
 __global__ __launch_bounds__(kVecThreads) void k_cg_dir(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     const SolveScalars& sc = it.sc[l.b];
     if (!sc.cg_active) return;
     const float bc = (float)sc.beta_cg;
-    const int npix = (int)it.npix;
+    const int nx = it.nx, ny = it.ny;
+    const int xc = min(l.x, nx - 1);
     const int64_t base = (int64_t)l.b * it.npix;
-    float2 d[kVecPix];
+    float2 d[kVecRows];
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int64_t o = base + min(pix_of(l, j), npix - 1);
-        const float2 r = it.r[o], p = it.p[o];
+    for (int j = 0; j < kVecRows; ++j) {
+        const int64_t o = base + (int64_t)load_row(l, j, ny) * nx + xc;
+        const float2 r = ld_nt(it.r + o), p = ld_nt(it.p + o);
         d[j] = make_float2(fmaf(bc, p.x, r.x), fmaf(bc, p.y, r.y));
     }
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = pix_of(l, j);
-        if (pix >= npix) break;
-        it.p[base + pix] = d[j];
+    for (int j = 0; j < kVecRows; ++j) {
+        if (!row_ok(l, j, ny)) break;
+        st_nt(it.p + base + (int64_t)(l.y0 + j) * nx + l.x, d[j]);
     }
 }
 
 // ---- eq. (8) and Alg. 4: eta += Theta rho' - mu; alpha; rho = rho' ------------
 __global__ __launch_bounds__(kVecThreads) void k_dual(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
     if (!it.sc[l.b].admm_active) return;
-    const int npix = (int)it.npix;
+    const int nx = it.nx, ny = it.ny;
+    const int xc = min(l.x, nx - 1);
     const int64_t base = (int64_t)l.b * it.npix;
     const float2* xn = it.xnew + base;
-    float2* eta = it.eta + (int64_t)l.b * 2 * it.npix;
-    const float2* mu = it.mu + (int64_t)l.b * 2 * it.npix;
-    float2 c[kVecPix], e0[kVecPix], e1[kVecPix], old[kVecPix];
+    float2* eta = it.eta + 2 * base;
+    const float2* mu = it.mu + 2 * base;
+    float2 c[kVecRows + 1], e0[kVecRows], e1[kVecRows], m0[kVecRows], m1[kVecRows], old[kVecRows], er[kVecRows];
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = min(pix_of(l, j), npix - 1);
-        const Nb n = neighbours(pix, it.nx, it.ny);
-        c[j] = xn[pix];
-        const float2 d0 = csub(xn[n.xp], c[j]), d1 = csub(xn[n.yp], c[j]);
-        e0[j] = cadd(eta[pix], csub(d0, mu[pix]));
-        e1[j] = cadd(eta[pix + it.npix], csub(d1, mu[pix + it.npix]));
-        old[j] = it.rho[base + pix];
+    for (int j = 0; j < kVecRows; ++j) er[j] = edge_right(xn, load_row(l, j, ny), nx, l);
+#pragma unroll
+    for (int i = 0; i <= kVecRows; ++i) c[i] = xn[(int64_t)load_row(l, i, ny) * nx + xc];
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) {
+        const int64_t pix = (int64_t)load_row(l, j, ny) * nx + xc;
+        e0[j] = ld_nt(eta + pix);
+        e1[j] = ld_nt(eta + it.npix + pix);
+        m0[j] = ld_nt(mu + pix);
+        m1[j] = ld_nt(mu + it.npix + pix);
+        old[j] = ld_nt(it.rho + base + pix);
     }
+    float2 rr[kVecRows];
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) rr[j] = right_of(l, nx, c[j], er[j]);
     double num = 0.0, den = 0.0;
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = pix_of(l, j);
-        if (pix >= npix) break;
-        eta[pix] = e0[j];
-        eta[pix + it.npix] = e1[j];
+    for (int j = 0; j < kVecRows; ++j) {
+        if (!row_ok(l, j, ny)) break;
+        const int64_t pix = (int64_t)(l.y0 + j) * nx + l.x;
+        st_nt(eta + pix, cadd(e0[j], csub(csub(rr[j], c[j]), m0[j])));
+        st_nt(eta + it.npix + pix, cadd(e1[j], csub(csub(c[j + 1], c[j]), m1[j])));
         num += cnorm2(csub(c[j], old[j]));
         den += cnorm2(old[j]);
-        it.rho[base + pix] = c[j];
+        st_nt(it.rho + base + pix, c[j]);
     }
     block_partials(num, den, it, l.b, l.blk);
 }
@@ -431,14 +525,14 @@ __global__ __launch_bounds__(kVecThreads) void k_finalize(const SolveTable tab, 
 
 // ---- output and per-slice report ---------------------------------------------
 __global__ __launch_bounds__(kVecThreads) void k_solve_final(const SolveTable tab) {
-    const Loc l = locate(tab);
+    const Tile l = locate(tab);
     const SolveItem& it = tab.it[l.item];
+    const int64_t base = (int64_t)l.b * it.npix;
 #pragma unroll
-    for (int j = 0; j < kVecPix; ++j) {
-        const int pix = pix_of(l, j);
-        if (pix >= (int)it.npix) break;
-        const int64_t o = (int64_t)l.b * it.npix + pix;
-        it.x_out[o] = it.rho[o];
+    for (int j = 0; j < kVecRows; ++j) {
+        if (!row_ok(l, j, it.ny)) break;
+        const int64_t o = base + (int64_t)(l.y0 + j) * it.nx + l.x;
+        it.x_out[o] = ld_nt(it.rho + o);
     }
     if (it.stats && l.blk == 0 && threadIdx.x == 0) {
         const SolveScalars& s = it.sc[l.b];
@@ -476,6 +570,23 @@ __global__ __launch_bounds__(kVecThreads) void k_sum_partials(const float2* __re
         si += v.y;
     }
     out[i] = make_float2((float)sr, (float)si);
+}
+
+// Periodic neighbours of pixel p in an ny x nx image (the single-operator
+// transforms, which run once per call).
+struct Nb {
+    int64_t xp, xm, yp, ym;   // (i, j+1), (i, j-1), (i+1, j), (i-1, j)
+};
+__device__ __forceinline__ Nb neighbours(int p, int nx, int ny) {
+    const int i = p / nx, j = p - i * nx;
+    const int jp = j + 1 == nx ? 0 : j + 1, jm = j == 0 ? nx - 1 : j - 1;
+    const int ip = i + 1 == ny ? 0 : i + 1, im = i == 0 ? ny - 1 : i - 1;
+    Nb n;
+    n.xp = (int64_t)i * nx + jp;
+    n.xm = (int64_t)i * nx + jm;
+    n.yp = (int64_t)ip * nx + j;
+    n.ym = (int64_t)im * nx + j;
+    return n;
 }
 
 __global__ __launch_bounds__(kVecThreads) void k_tv_forward(int nx, int ny, const float2* __restrict__ x,

@@ -4,6 +4,7 @@
     python -m paper_2006_14080_amd.profsum pmc <run_counter_collection.csv> --cmd "<command>"
     python -m paper_2006_14080_amd.profsum traffic <fetch.csv> <write.csv> --cmd "<command>" [--json out.json --key fp32]
     python -m paper_2006_14080_amd.profsum vecbw <run_kernel_stats.csv> <run log> --cmd "<command>" [--copy-bytes B]
+                                           [--fetch <FETCH_SIZE csv> --write <WRITE_SIZE csv>]
     python -m paper_2006_14080_amd.profsum busy <run_kernel_trace.csv> --cmd "<command>"
     python -m paper_2006_14080_amd.profsum grid <run_kernel_trace.csv> --cmd "<command>"
 
@@ -113,7 +114,8 @@ VEC_BYTES = {
     "k_cg_update": lambda c, p: 4 * 8 + 2 * 8,         # x, r, d, A d -> x, r
     "k_cg_dir": lambda c, p: 2 * 8 + 8,                # r, d -> d
     "k_dual": lambda c, p: 8 + 16 + 16 + 8 + 16 + 8,   # x, mu, eta, rho -> eta, rho
-    "k_coil_weight": lambda c, p: 8 + 16 * c,          # x, s -> s (.) x
+    "k_coil_weight": lambda c, p: 8 + 8 * c,           # x -> s (.) x per coil (the profiled workloads share
+                                                       # one map set over all slices: read once, not per pixel)
 }
 HBM_PEAK = 8.0e12
 
@@ -131,9 +133,31 @@ def run_sizes(log_path):
     return found
 
 
-def vecbw(path, npix, coils, planes, copy_bytes=None):
+# HBM bytes from the counters: FETCH_SIZE x 2 (it counts each 128-byte read
+# request as 64 bytes) + WRITE_SIZE x 1.  Measured on the multi-GB sweep, where
+# the memory-bound kernels' reads and writes are known exactly: k_cg_update
+# (32 B/px read, 16 written), k_dual (48, 24), k_adj_finish<2> (16, 8) read
+# exactly twice their raw FETCH_SIZE and write exactly their raw WRITE_SIZE.
+# (A device copy cannot calibrate this at these sizes: the 256 MB Infinity
+# Cache serves part of its reads and absorbs part of its writes.)
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
+
+
+def vecbw(path, npix, coils, planes, copy_bytes=None, fetch_csv=None, write_csv=None):
+    """Per memory-bound kernel: algorithmic bytes per pixel, achieved GB/s and
+    fraction of the HBM peak; with FETCH_SIZE / WRITE_SIZE counter runs of the
+    same command, also the HBM bytes per pixel the counters measured."""
     rows = list(csv.DictReader(open(path)))
-    out = [f"{'kernel':16s} {'calls':>6s} {'avg_us':>9s} {'bytes/px':>9s} {'GB/s':>8s} {'of 8 TB/s':>9s}"]
+    meas = {}
+    if fetch_csv and write_csv:
+        f = _per_kernel(fetch_csv, "FETCH_SIZE")
+        w = _per_kernel(write_csv, "WRITE_SIZE")
+        cf, cw = FETCH_SCALE, WRITE_SCALE
+        for k in f:
+            if k in w and k != COPY_KERNEL:
+                meas[k.split("(")[0].replace("void ", "").strip()] = (f[k] * 1024.0 * cf + w[k] * 1024.0 * cw) / npix
+    head = f"{'kernel':16s} {'calls':>6s} {'avg_us':>9s} {'bytes/px':>9s} {'GB/s':>8s} {'of 8 TB/s':>9s}"
+    out = [head + (f" {'HBM B/px (counters)':>20s}" if meas else "")]
     if copy_bytes:
         # a device copy of copy_bytes read + copy_bytes written, in the same run
         for r in rows:
@@ -151,7 +175,10 @@ def vecbw(path, npix, coils, planes, copy_bytes=None):
         if gbs * 1e9 > HBM_PEAK:
             raise SystemExit(f"{k}: {gbs:.0f} GB/s exceeds the HBM peak; its byte count "
                              f"({b} B/px, {planes} planes) does not match the run")
-        out.append(f"{k:16s} {int(r['Calls']):6d} {us:9.2f} {b:9d} {gbs:8.1f} {gbs * 1e9 / HBM_PEAK:9.1%}")
+        line = f"{k:16s} {int(r['Calls']):6d} {us:9.2f} {b:9d} {gbs:8.1f} {gbs * 1e9 / HBM_PEAK:9.1%}"
+        if meas:
+            line += f" {meas.get(k, float('nan')):20.1f}"
+        out.append(line)
     return out
 
 
@@ -268,6 +295,8 @@ def main():
     ap.add_argument("--json")
     ap.add_argument("--key")
     ap.add_argument("--copy-bytes", type=int, help="vecbw: size of the reference device copy in the run")
+    ap.add_argument("--fetch", help="vecbw: FETCH_SIZE counter csv of the same command")
+    ap.add_argument("--write", help="vecbw: WRITE_SIZE counter csv of the same command")
     a = ap.parse_args()
     if a.mode == "vecbw":
         npix, coils, planes = run_sizes(a.csv2)
@@ -275,7 +304,10 @@ def main():
         print(f"# command: {a.cmd}")
         print(f"# pixels (all slices) = {npix}, coils = {coils}, adjoint partial images per slice = {planes} "
               "(as printed by the run)")
-        for line in vecbw(a.csv, npix, coils, planes, a.copy_bytes):
+        if a.fetch:
+            print(f"# HBM bytes from FETCH_SIZE / WRITE_SIZE runs of the same command: FETCH_SIZE x {FETCH_SCALE:g} "
+                  f"+ WRITE_SIZE x {WRITE_SCALE:g} (KiB per dispatch)")
+        for line in vecbw(a.csv, npix, coils, planes, a.copy_bytes, a.fetch, a.write):
             print(line)
         return 0
     if a.mode == "busy":
