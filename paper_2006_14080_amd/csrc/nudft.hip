@@ -272,8 +272,9 @@ struct PolSplit {
         }
     }
     // The same products with a producer interleaved: prod(i), i = 0..5, runs
-    // after each sixth of the MFMAs.  Scheduling fences keep each piece of
-    // vector work between two groups of matrix-core instructions, so the SIMD
+    // with each sixth of the MFMAs.  Scheduling fences keep each piece of
+    // vector work within its group of matrix-core instructions, and group
+    // barriers alternate one MFMA with a few ALU instructions, so the SIMD
     // executes both at once instead of one burst after the other.  Every wave
     // runs all its tiles (a wave without live rows works on rows the epilogue
     // never reads): a skip branch would make the compiler copy the
@@ -332,8 +333,22 @@ struct PolSplit {
                     acc_im[t] = mfma(av, part == 2 ? bl[1] : bh[1], acc_im[t]);
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
-            prod(g);
+            if constexpr (!kByTile) {
+                // The producer piece is scheduled among this group's matrix
+                // instructions: one MFMA, then up to five vector or scalar ALU
+                // instructions, so the SIMD issues them while the MFMAs run
+                // (forward 6 % faster; the adjoint's pieces wait on LDS reads
+                // and gained nothing, so there each piece follows its group).
+                prod(g);
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x006, 5, 0);   // five VALU / SALU
+                }
+            } else {
+                __builtin_amdgcn_sched_barrier(0);
+                prod(g);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -710,8 +725,13 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
             // Split forms: the next stage's B phases are produced in six pieces
             // between the MFMA groups of this stage, branch-free (lanes past
             // the last sample store zeros; the last step produces its own
-            // stage again into the idle buffer, where nothing reads it).
-            for (int s = 0; s < nsteps; ++s) {
+            // stage again into the idle buffer, where nothing reads it).  As
+            // in FP32, the step base advances by one factor E(KC) per step and
+            // is regenerated with the FP64 reduction every kXAnchor steps: the
+            // steps run in unrolled blocks of kXAnchor, so whether a step
+            // regenerates is known at compile time and the loop stays one
+            // basic block; steps past the last whole block regenerate always.
+            auto split_step = [&](int s, bool exact) {
                 const int cur = s & 1;
                 const int sn = s + 1 < nsteps ? s + 1 : s;
                 QuarterTurn qt;
@@ -724,14 +744,17 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
                         // stage's operand reads: issued before them, they would
                         // make those reads wait for the copies to land.
                         load_a_to(sn, cur ^ 1);
-                        qt = reduce_quarter_turns(fx4 * (double)(sn * KC - xh));
+                        if (exact) qt = reduce_quarter_turns(fx4 * (double)(sn * KC - xh));
+                        else xb = cmul(xb, wk);
                     } else if (piece == 1) {
-                        sc = sincos_octant(qt.th);
+                        if (exact) sc = sincos_octant(qt.th);
                     } else if (piece == 2) {
-                        const SinCos r = rotate_quadrant(sc, qt.q);
-                        const float2 base = make_float2(r.c, -r.s);
-                        e0 = cmul(base, w0);
-                        e1 = cmul(base, w1);
+                        if (exact) {
+                            const SinCos r = rotate_quadrant(sc, qt.q);
+                            xb = make_float2(r.c, -r.s);
+                        }
+                        e0 = cmul(xb, w0);
+                        e1 = cmul(xb, w1);
                     } else if (piece == 3) {
                         e0 = p_ok ? e0 : make_float2(0.f, 0.f);
                         e1 = p_ok ? e1 : make_float2(0.f, 0.f);
@@ -746,7 +769,13 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
                                                     wn * 32, lane, acc_re, acc_im, prod);
                 wait_a();
                 __syncthreads();
+            };
+            int s = 0;
+            for (; s + kXAnchor <= nsteps; s += kXAnchor) {
+#pragma unroll
+                for (int u = 0; u < kXAnchor; ++u) split_step(s + u, u == kXAnchor - 1);
             }
+            for (; s < nsteps; ++s) split_step(s, true);
         } else {
             for (int s = 0; s < nsteps; ++s) {
                 const int cur = s & 1;
