@@ -53,7 +53,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2516.6, "fp16x3": 2516.6}   # MI355X dense MFMA peaks
-DTYPE = {"fp32": "f32", "bf16x3": "bf16x3", "fp16x3": "f16x3"}
+DTYPE = {"fp32": "f32", "bf16x3": "bf16x3", "fp16x3": "f16x3", "nufft": "f32"}
 # Oracle data and 30 x 5 reconstruction of the 256x256 problem
 # (written by tests/golden/make_admm256_golden.py).
 GOLDEN_ADMM256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "admm256_oracle.npz")
@@ -68,7 +68,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp16x3"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16x3", "fp16x3", "nufft"], default="fp32",
+                    help="NUDFT arithmetic form, or nufft: F by the NUFFT operator (width 6, oversampling 2)")
     ap.add_argument("--workload", choices=["admm256", "slices384", "table1_1024x512", "serve"],
                     default="admm256")
     ap.add_argument("--requests", type=int, default=24, help="serve: requests in the replayed stream")
@@ -428,11 +429,16 @@ def main():
 
     dtmp = torch.empty_like(data)
     img = out.clone()
-    fwd_ms = timed(lambda: mri.nudft_forward(img, sm, tr, precision=prec, out=dtmp), args.kernel_launches)
-    # The adjoint as the solve applies it: phase tables built once for the
-    # trajectory, then the adjoint kernel and its fixed-order reduction.
-    adj = mri.AdjointPlan(sm, tr, wl.ny, wl.nx, precision=prec)
-    adj_ms = timed(lambda: adj(data, out=img), args.kernel_launches)
+    if prec == mri.NUFFT:
+        nplan = mri.NufftPlan(sm, tr, wl.ny, wl.nx)
+        fwd_ms = timed(lambda: nplan.forward(img, out=dtmp), args.kernel_launches)
+        adj_ms = timed(lambda: nplan.adjoint(data, out=img), args.kernel_launches)
+    else:
+        fwd_ms = timed(lambda: mri.nudft_forward(img, sm, tr, precision=prec, out=dtmp), args.kernel_launches)
+        # The adjoint as the solve applies it: phase tables built once for the
+        # trajectory, then the adjoint kernel and its fixed-order reduction.
+        adj = mri.AdjointPlan(sm, tr, wl.ny, wl.nx, precision=prec)
+        adj_ms = timed(lambda: adj(data, out=img), args.kernel_launches)
     flop = wl.nudft_flop
     dom_name, dom_ms = ("nudft_forward", fwd_ms) if fwd_ms >= adj_ms else ("nudft_adjoint", adj_ms)
     achieved = flop / (dom_ms / 1e3) / 1e12
@@ -440,7 +446,7 @@ def main():
         achieved_pipe = achieved * 3.0      # three 16-bit products per real product
     else:
         achieved_pipe = achieved
-    peak = PEAK_TFLOPS[args.precision]
+    peak = PEAK_TFLOPS.get(args.precision)
     # HBM bytes per launch from FETCH_SIZE / WRITE_SIZE (copy-calibrated), valid
     # only while the kernel sources match the ones the counters were taken on.
     traffic = None
@@ -472,10 +478,10 @@ def main():
                    "readout": wl.n_readout, "admm_iters": wl.admm_iters, "cg_iters": wl.cg_iters,
                    "lambda": wl.lam, "beta": wl.beta, "precision": args.precision,
                    "nudft_calls_per_step": wl.nudft_calls},
-        "roofline": {"bound": "mfma", "kernel": dom_name, "achieved": achieved_pipe, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved_pipe / peak, "traffic": traffic,
-                     "algorithmic_tflop_per_launch": flop / 1e12,
-                     "avg_launch_ms": dom_ms},
+        "roofline": ({"bound": "mfma", "kernel": dom_name, "achieved": achieved_pipe, "peak": peak,
+                      "unit": "TFLOP/s", "frac": achieved_pipe / peak, "traffic": traffic,
+                      "algorithmic_tflop_per_launch": flop / 1e12,
+                      "avg_launch_ms": dom_ms} if peak else None),
         "kernels_ms": {"nudft_forward": fwd_ms, "nudft_adjoint": adj_ms,
                        "fp32_equiv_tflops": {"nudft_forward": flop / fwd_ms / 1e9,
                                              "nudft_adjoint": flop / adj_ms / 1e9}},
@@ -483,9 +489,13 @@ def main():
         "image_nrmse_vs_oracle": nrmse,
         "image_nrmse_vs_phantom": nrmse_truth,
     }
-    if not args.no_equal_nrmse:
+    if prec == mri.NUFFT:
+        rec["note"] = ("F by the NUFFT operator (Kaiser-Bessel width 6, oversampling 2, FP32): its kernels are "
+                       "grid, FFT and gather passes, not a matrix product, so no MFMA roofline; kernels_ms holds "
+                       "its forward and adjoint times and fp32_equiv_tflops the dense product's flop over them")
+    if not args.no_equal_nrmse and prec != mri.NUFFT:
         rec["forms_at_equal_nrmse"] = forms_at_equal_nrmse(wl, sm, tr, data, truth0)
-    if not args.no_serve_latency:
+    if not args.no_serve_latency and prec != mri.NUFFT:
         # The latency half of the metric: a short Poisson trace of mixed-shape
         # requests (128/256/384 px, 4-32 coils, 32-128 spokes, 30 x 5 each) at
         # an arrival rate under the form's saturation knee, replayed in wall-clock

@@ -63,9 +63,12 @@ enum {
     MRI_BF16X3 = 1, /* split-BF16 compensated products (hi*hi + hi*lo + lo*hi)
                        on BF16 MFMA, FP32 accumulation (Sec. II-A); about 16
                        bits per operand */
-    MRI_FP16X3 = 2  /* the same split products with fp16 parts on FP16 MFMA
+    MRI_FP16X3 = 2, /* the same split products with fp16 parts on FP16 MFMA
                        (same rate): about 22 bits per operand; operands are
                        scaled by exact powers of two into fp16's range */
+    MRI_NUFFT = 3   /* admm_solve only: F applied by the NUFFT operator
+                       (nufft_*, width 6, oversampling 2, FP32) instead of
+                       the dense NUDFT; one problem per call (any batch) */
 };
 
 enum {
@@ -273,7 +276,7 @@ typedef struct {
 enum { MRI_REQ_UNKNOWN = -1, MRI_REQ_QUEUED = 0, MRI_REQ_RUNNING = 1, MRI_REQ_DONE = 2 };
 
 /* Create a server.  precision: MRI_FP32, MRI_BF16X3 or MRI_FP16X3 for all
- * its requests.  stream: the hipStream_t every copy, launch and graph replay
+ * its requests (MRI_NUFFT is not served: MRI_ENOTSUP).  stream: the hipStream_t every copy, launch and graph replay
  * of the server goes to (it must stay valid until mri_server_destroy and
  * must not be the legacy default stream, which cannot be captured); NULL =
  * the server creates and owns a non-blocking stream of its own.
@@ -309,6 +312,61 @@ int mri_server_destroy(void* srv);
 /* Workspace bytes needed by an operation (params may be NULL except for
  * MRI_OP_ADMM).  Returns 0 for an invalid shape. */
 size_t mri_workspace_bytes(const mri_shape* shape, int op, const mri_admm_params* params);
+
+/* ---------------------------------------------------------------------------
+ * NUFFT operator: the O(N log N) approximation of F used by the paper's
+ * comparison systems (Sec. VII, Table II), as an alternative to the dense
+ * nudft_* operators, with the same shapes, layouts and conventions.
+ *
+ * Forward, per slice and coil: the coil-weighted image divided by the
+ * kernel's Fourier transform (deapodisation) is zero-padded into a grid of
+ * G = the smallest power of two >= sigma * n (at least 16) per axis, FFTed
+ * (exp(-2 pi i m x / G)), and each sample interpolates its (W+1) x (W+1)
+ * nearest grid points with the Kaiser-Bessel kernel
+ *   psi(u) = I0(beta sqrt(1 - (2u/W)^2)),  |u| <= W/2,
+ *   beta = pi sqrt(W^2 (s - 1/2)^2 / s^2 - 0.8),  s = G / n,
+ * at the sample's grid position t = w G / (2 pi).  The adjoint is its exact
+ * conjugate transpose (spreading, inverse FFT, crop, deapodisation, conj(s)
+ * coil combine).  Relative error against the exact NUDFT: about 2e-6
+ * (forward) and 5e-6 (adjoint) at W = 6, sigma = 2, and near ten times less
+ * per extra point of width (W = 7: below 1e-6).  Spreading is deterministic:
+ * every grid point sums the samples that reach it in sample order, so
+ * results are bitwise reproducible run to run.
+ *
+ * A workspace of mri_nufft_workspace_bytes(shape, params) holds the plan
+ * (per trajectory: each sample's neighbours and kernel weights, the samples
+ * of every 16 x 16 grid tile sorted by index; deapodisation; FFT twiddles)
+ * and the grid ([B][nc][Gy][Gx] complex64).  nufft_prepare builds the plan
+ * from the trajectory (traj as for nudft_*, per slice when traj_batched);
+ * nufft_forward / nufft_adjoint apply the operator with the plan already in
+ * ws (same shape and params, prepared on the same stream or synchronised),
+ * and overwrite only the grid, so they may follow each other.
+ * --------------------------------------------------------------------------- */
+typedef struct {
+    int32_t width;        /* W, kernel width in grid points: 2 .. 10 (6 by default) */
+    int32_t pad;
+    double sigma;         /* oversampling: 1.25 .. 4 (2 by default); G <= 4096 */
+} mri_nufft_params;
+
+/* Workspace bytes of the NUFFT for a shape and parameters (0 when invalid or
+ * unsupported). */
+size_t mri_nufft_workspace_bytes(const mri_shape* shape, const mri_nufft_params* params);
+
+/* Build the plan for shape / traj / params in ws.
+ * Errors: MRI_EINVAL (null pointer, bad shape or params), MRI_ENOTSUP (grid
+ * side above 4096 or too many samples), MRI_ENOMEM (ws too small), MRI_EHIP. */
+int nufft_prepare(const mri_shape* shape, const double* traj, const mri_nufft_params* params,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* y ~ F(x): x [B][ny][nx], smaps [B or 1][nc][ny][nx], y [B][nc][nk]
+ * (written).  Errors: as nufft_prepare. */
+int nufft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps, mri_c32* y,
+                  const mri_nufft_params* params, void* ws, size_t ws_bytes, void* stream);
+
+/* x ~ F^H(y), the exact adjoint of nufft_forward: y [B][nc][nk], x
+ * [B][ny][nx] (written).  Errors: as nufft_prepare. */
+int nufft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps, mri_c32* x,
+                  const mri_nufft_params* params, void* ws, size_t ws_bytes, void* stream);
 
 /* Sample-range split of nudft_adjoint for a shape (the same for every
  * precision): *ksplit sample ranges of *kper samples each, and *planes

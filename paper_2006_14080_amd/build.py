@@ -16,7 +16,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmriadmm.so")
-SOURCES = ["api.hip", "plan.hip", "server.hip", "nudft.hip", "solver.hip"]
+SOURCES = ["api.hip", "plan.hip", "server.hip", "nudft.hip", "solver.hip", "nufft.hip"]
 ARCH = "gfx950"
 
 

@@ -7,6 +7,7 @@
 #include <mutex>
 #include <string>
 
+#include "nufft.h"
 #include "plan.h"
 
 namespace mri {
@@ -109,6 +110,55 @@ int mri_adjoint_split(const mri_shape* shape, int32_t* ksplit, int32_t* kper, in
     if (ksplit) *ksplit = ks;
     if (kper) *kper = kp;
     if (planes) *planes = adj_partial_planes(shape->ncoils, ks);
+    return MRI_OK;
+}
+
+size_t mri_nufft_workspace_bytes(const mri_shape* shape, const mri_nufft_params* params) {
+    if (check_shape(shape) != MRI_OK || !params) return 0;
+    NufftLayout L;
+    if (nufft_layout(*shape, *params, &L) != MRI_OK) return 0;
+    return L.total;
+}
+
+int nufft_prepare(const mri_shape* shape, const double* traj, const mri_nufft_params* params, void* ws,
+                  size_t ws_bytes, void* stream) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if (!traj || !params) return MRI_EINVAL;
+    NufftLayout L;
+    if ((rc = nufft_layout(*shape, *params, &L))) return rc;
+    if (!ws || ws_bytes < L.total) return MRI_ENOMEM;
+    MRI_HIP(launch_nufft_prepare(L, nufft_ptrs(L, ws), traj, static_cast<hipStream_t>(stream)));
+    return MRI_OK;
+}
+
+int nufft_forward(const mri_shape* shape, const mri_c32* x, const mri_c32* smaps, mri_c32* y,
+                  const mri_nufft_params* params, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if (!x || !smaps || !y || !params) return MRI_EINVAL;
+    NufftLayout L;
+    if ((rc = nufft_layout(*shape, *params, &L))) return rc;
+    if (!ws || ws_bytes < L.total) return MRI_ENOMEM;
+    const int64_t sbs = shape->smaps_batched ? (int64_t)shape->ncoils * shape->nx * shape->ny : 0;
+    MRI_HIP(launch_nufft_forward(L, nufft_ptrs(L, ws), reinterpret_cast<const float2*>(x),
+                                 reinterpret_cast<const float2*>(smaps), sbs, reinterpret_cast<float2*>(y),
+                                 static_cast<hipStream_t>(stream)));
+    return MRI_OK;
+}
+
+int nufft_adjoint(const mri_shape* shape, const mri_c32* y, const mri_c32* smaps, mri_c32* x,
+                  const mri_nufft_params* params, void* ws, size_t ws_bytes, void* stream) {
+    int rc = check_shape(shape);
+    if (rc) return rc;
+    if (!x || !smaps || !y || !params) return MRI_EINVAL;
+    NufftLayout L;
+    if ((rc = nufft_layout(*shape, *params, &L))) return rc;
+    if (!ws || ws_bytes < L.total) return MRI_ENOMEM;
+    const int64_t sbs = shape->smaps_batched ? (int64_t)shape->ncoils * shape->nx * shape->ny : 0;
+    MRI_HIP(launch_nufft_adjoint(L, nufft_ptrs(L, ws), reinterpret_cast<const float2*>(y),
+                                 reinterpret_cast<const float2*>(smaps), sbs, reinterpret_cast<float2*>(x),
+                                 static_cast<hipStream_t>(stream)));
     return MRI_OK;
 }
 

@@ -27,6 +27,10 @@ int check_precision(int p) {
     return MRI_EINVAL;
 }
 
+int check_solve_precision(int p) {
+    return p == MRI_NUFFT ? MRI_OK : check_precision(p);
+}
+
 int check_params(const mri_admm_params* p) {
     if (!p) return MRI_EINVAL;
     if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return MRI_EINVAL;
@@ -34,7 +38,7 @@ int check_params(const mri_admm_params* p) {
     if (p->admm_iters < 0 || p->cg_iters < 0) return MRI_EINVAL;
     if (!(p->rtol >= 0.0) || !(p->atol >= 0.0)) return MRI_EINVAL;
     if (p->cg_warm_start != 0 && p->cg_warm_start != 1) return MRI_EINVAL;
-    return check_precision(p->precision);
+    return check_solve_precision(p->precision);
 }
 
 size_t forward_ws(const mri_shape& s) {
@@ -65,12 +69,31 @@ void bind_adj_tables(NudftItem& it, const mri_shape& s, void* part) {
     it.ephy_bs = s.traj_batched ? s.nk * s.ny : 0;
 }
 
+// The NUFFT parameters of the MRI_NUFFT solve mode.
+mri_nufft_params solve_nufft_params() {
+    mri_nufft_params p;
+    p.width = 6;
+    p.pad = 0;
+    p.sigma = 2.0;
+    return p;
+}
+
 AdmmLayout admm_layout(const mri_shape& s, int precision) {
     AdmmLayout L;
+    std::memset(&L, 0, sizeof(L));
     const int64_t npix = (int64_t)s.nx * s.ny;
     const size_t vec = ws_align(sizeof(float2) * npix * s.batch);
-    adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, precision, &L.ksplit, &L.kper);
-    L.nplanes = adj_partial_planes(s.ncoils, L.ksplit);
+    const bool nufft = precision == MRI_NUFFT;
+    NufftLayout nl;
+    if (nufft) {
+        if (nufft_layout(s, solve_nufft_params(), &nl) != MRI_OK) return L;   // total 0: unsupported
+        L.ksplit = 1;
+        L.kper = (int32_t)s.nk;
+        L.nplanes = 1;
+    } else {
+        adj_split(s.nx, s.ny, s.ncoils, s.nk, s.batch, precision, &L.ksplit, &L.kper);
+        L.nplanes = adj_partial_planes(s.ncoils, L.ksplit);
+    }
     L.nblk = (int32_t)vec_tiles(s.nx, s.ny);
     size_t o = 0;
     L.rho = o;  o += vec;
@@ -84,8 +107,13 @@ AdmmLayout admm_layout(const mri_shape& s, int precision) {
     L.eta = o;  o += 2 * vec;
     L.mu = o;   o += 2 * vec;
     L.dtmp = o; o += ws_align(sizeof(float2) * (size_t)s.ncoils * s.nk * s.batch);
-    L.wimg = o; o += forward_ws(s);
-    L.part = o; o += adjoint_ws(s);
+    if (nufft) {
+        L.part = o;  o += vec;
+        L.nufft = o; o += ws_align(nl.total);
+    } else {
+        L.wimg = o; o += forward_ws(s);
+        L.part = o; o += adjoint_ws(s);
+    }
     L.red = o;  o += ws_align(sizeof(double) * 2 * (size_t)L.nblk * s.batch);
     L.sc = o;   o += ws_align(sizeof(SolveScalars) * (size_t)s.batch);
     L.total = o;
@@ -113,6 +141,7 @@ void append(NudftTable& t, const NudftItem& it, int64_t ntiles, int64_t cw_elems
 
 int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
     if (n < 1 || n > kMaxItems) return MRI_EINVAL;
+    if (precision == MRI_NUFFT && n != 1) return MRI_ENOTSUP;    // the NUFFT mode plans one problem
     for (int i = 0; i < n; ++i)
         if ((int64_t)bind[i].shape.nx * bind[i].shape.ny >= ((int64_t)1 << 31)) return MRI_ENOTSUP;
     Plan& P = *out;
@@ -125,6 +154,7 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         const mri_shape& sh = B.shape;
         const mri_admm_params& prm = B.params;
         const AdmmLayout L = admm_layout(sh, precision);
+        if (L.total == 0) return MRI_ENOTSUP;
         const int64_t npix = (int64_t)sh.nx * sh.ny;
         void* ws = B.ws;
 
@@ -205,6 +235,19 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         append(P.ainit, f_init, at_, 0);
         append(P.fstep, f_step, ft, cw);
         append(P.astep, f_step, at_, 0);
+        if (precision == MRI_NUFFT) {
+            P.nufft = true;
+            if (nufft_layout(sh, solve_nufft_params(), &P.nl) != MRI_OK) return MRI_ENOTSUP;
+            P.np = nufft_ptrs(P.nl, at<char>(ws, L.nufft));
+            P.traj = B.traj;
+            P.smaps = B.smaps;
+            P.smaps_bs = base.smaps_bs;
+            P.y = B.y;
+            P.dtmp = at<float2>(ws, L.dtmp);
+            P.part = si.part;
+            P.src_init = f_init.img;
+            P.src_step = si.p;
+        }
     }
     if (blocks > (int64_t)1 << 30 || tiles_f > (int64_t)1 << 30 || tiles_a > (int64_t)1 << 30)
         return MRI_ENOTSUP;
@@ -220,10 +263,29 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         if (e_ != hipSuccess) return e_;       \
     } while (0)
 
+// F^H F applied to src: the adjoint's output lands in the partial-image
+// plane(s) that k_adj_finish sums.
+hipError_t enqueue_normal(const Plan& p, const NudftTable& f, const NudftTable& a, const float2* src,
+                          hipStream_t s) {
+    if (p.nufft) {
+        PLAN_TRY(launch_nufft_forward(p.nl, p.np, src, p.smaps, p.smaps_bs, p.dtmp, s));
+        return launch_nufft_adjoint(p.nl, p.np, p.dtmp, p.smaps, p.smaps_bs, p.part, s);
+    }
+    PLAN_TRY(launch_coil_weight(f, p.precision, s));
+    PLAN_TRY(launch_nudft_forward(f, p.precision, s));
+    return launch_nudft_adjoint(a, p.precision, s);
+}
+
 hipError_t enqueue_init(const Plan& p, hipStream_t s) {
-    PLAN_TRY(launch_adj_phases(p.afhd, s));     // the trajectory is fixed for the solve
-    PLAN_TRY(launch_solve_init(p.st, s));
-    PLAN_TRY(launch_nudft_adjoint(p.afhd, p.precision, s));
+    if (p.nufft) {
+        PLAN_TRY(launch_nufft_prepare(p.nl, p.np, p.traj, s));      // the trajectory is fixed for the solve
+        PLAN_TRY(launch_solve_init(p.st, s));
+        PLAN_TRY(launch_nufft_adjoint(p.nl, p.np, p.y, p.smaps, p.smaps_bs, p.part, s));
+    } else {
+        PLAN_TRY(launch_adj_phases(p.afhd, s));                     // the trajectory is fixed for the solve
+        PLAN_TRY(launch_solve_init(p.st, s));
+        PLAN_TRY(launch_nudft_adjoint(p.afhd, p.precision, s));
+    }
     PLAN_TRY(launch_adj_finish(p.st, kFinishFhd, s));
     return hipSuccess;
 }
@@ -231,15 +293,11 @@ hipError_t enqueue_init(const Plan& p, hipStream_t s) {
 hipError_t enqueue_iteration(const Plan& p, hipStream_t s) {
     PLAN_TRY(launch_mu(p.st, s));
     PLAN_TRY(launch_rhs(p.st, s));
-    PLAN_TRY(launch_coil_weight(p.finit, p.precision, s));
-    PLAN_TRY(launch_nudft_forward(p.finit, p.precision, s));
-    PLAN_TRY(launch_nudft_adjoint(p.ainit, p.precision, s));
+    PLAN_TRY(enqueue_normal(p, p.finit, p.ainit, p.src_init, s));
     PLAN_TRY(launch_adj_finish(p.st, kFinishCgInit, s));
     PLAN_TRY(launch_finalize(p.st, kFinCgInit, s));
     for (int j = 0; j < p.max_cg; ++j) {
-        PLAN_TRY(launch_coil_weight(p.fstep, p.precision, s));
-        PLAN_TRY(launch_nudft_forward(p.fstep, p.precision, s));
-        PLAN_TRY(launch_nudft_adjoint(p.astep, p.precision, s));
+        PLAN_TRY(enqueue_normal(p, p.fstep, p.astep, p.src_step, s));
         PLAN_TRY(launch_adj_finish(p.st, kFinishCgStep, s));
         PLAN_TRY(launch_finalize(p.st, kFinCgStep, s));
         PLAN_TRY(launch_cg_update(p.st, s));

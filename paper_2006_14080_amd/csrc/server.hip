@@ -245,6 +245,7 @@ size_t mri_server_request_bytes(const mri_shape* shape, int precision) {
 
 int mri_server_create(size_t hbm_budget, int max_slots, int precision, void* stream, void** srv) {
     if (!srv || max_slots < 1 || max_slots > kMaxItems || hbm_budget < kWsAlign) return MRI_EINVAL;
+    if (precision == MRI_NUFFT) return MRI_ENOTSUP;
     int rc = check_precision(precision);
     if (rc) return rc;
     Server* S = new (std::nothrow) Server();

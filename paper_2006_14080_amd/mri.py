@@ -25,7 +25,8 @@ LIB_PATH = os.path.join(_HERE, "libmriadmm.so")
 FP32 = 0
 BF16X3 = 1
 FP16X3 = 2
-PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
+NUFFT = 3            # admm_solve only: F by the NUFFT operator (width 6, oversampling 2, FP32)
+PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3, "nufft": NUFFT}
 PRECISION_NAMES = {v: k for k, v in PRECISIONS.items()}
 
 OP_FORWARD, OP_ADJOINT, OP_ADMM = 0, 1, 2
@@ -53,11 +54,16 @@ class MriAdmmStats(ctypes.Structure):
                 ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+class MriNufftParams(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("pad", ctypes.c_int32), ("sigma", ctypes.c_double)]
+
+
 STATS_BYTES = ctypes.sizeof(MriAdmmStats)
 
 EXPORTS = ["nudft_forward", "nudft_forward_noalloc", "mri_noalloc_scratch_bytes", "nudft_adjoint", "nudft_adjoint_prepare", "nudft_adjoint_prepared",
            "tv_forward", "tv_adjoint", "admm_solve", "mri_workspace_bytes", "mri_adjoint_split",
-           "mri_strerror", "mri_last_hip_error"]
+           "mri_strerror", "mri_last_hip_error", "mri_nufft_workspace_bytes", "nufft_prepare", "nufft_forward",
+           "nufft_adjoint"]
 
 _lib = None
 
@@ -93,6 +99,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.admm_solve.argtypes = [shp, vp, vp, vp, vp, prm, vp, vp, vp, sz, vp]
     lib.mri_workspace_bytes.argtypes = [shp, i32, prm]
     lib.mri_workspace_bytes.restype = sz
+    nup = ctypes.POINTER(MriNufftParams)
+    lib.mri_nufft_workspace_bytes.argtypes = [shp, nup]
+    lib.mri_nufft_workspace_bytes.restype = sz
+    lib.nufft_prepare.argtypes = [shp, vp, nup, vp, sz, vp]
+    lib.nufft_forward.argtypes = [shp, vp, vp, vp, nup, vp, sz, vp]
+    lib.nufft_adjoint.argtypes = [shp, vp, vp, vp, nup, vp, sz, vp]
+    for name in ["nufft_prepare", "nufft_forward", "nufft_adjoint"]:
+        getattr(lib, name).restype = i32
     i32p = ctypes.POINTER(ctypes.c_int32)
     lib.mri_adjoint_split.argtypes = [shp, i32p, i32p, i32p]
     lib.mri_adjoint_split.restype = i32
@@ -296,6 +310,56 @@ class AdjointPlan:
         _check(load().nudft_adjoint_prepared(ctypes.byref(sh), _ptr(data), _ptr(self.smaps), _ptr(self.traj),
                                              _ptr(out), self.precision, _ptr(self.ws), self.ws_bytes,
                                              _stream()), "nudft_adjoint_prepared")
+        return out
+
+
+class NufftPlan:
+    """The NUFFT operator (nufft_prepare / nufft_forward / nufft_adjoint) for
+    fixed maps, trajectory, image size and batch: the plan and the grid live in
+    a workspace this object owns, built once here."""
+
+    def __init__(self, smaps: torch.Tensor, traj: torch.Tensor, ny: int, nx: int, batch: int = 1,
+                 width: int = 6, sigma: float = 2.0):
+        self.shape = shape_of((batch, ny, nx), smaps, traj)
+        _check_inputs(self.shape, smaps, traj)
+        _on_gpu(smaps=smaps, traj=traj)
+        self.smaps, self.traj = smaps, traj
+        self.params = MriNufftParams(int(width), 0, float(sigma))
+        lib = load()
+        n = int(lib.mri_nufft_workspace_bytes(ctypes.byref(self.shape), ctypes.byref(self.params)))
+        if n == 0:
+            raise ValueError("unsupported NUFFT shape or parameters")
+        self.ws = torch.empty(n, dtype=torch.uint8, device=smaps.device)
+        self.ws_bytes = n
+        _check(lib.nufft_prepare(ctypes.byref(self.shape), _ptr(traj), ctypes.byref(self.params), _ptr(self.ws),
+                                 n, _stream()), "nufft_prepare")
+
+    def forward(self, image: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y ~ F(image): [B, ny, nx] -> [B, nc, nk]."""
+        sh = self.shape
+        _need(image, torch.complex64, "image", (sh.batch, sh.ny, sh.nx))
+        if out is not None:
+            _need(out, torch.complex64, "out", (sh.batch, sh.ncoils, sh.nk))
+        _on_gpu(self.smaps.device, image=image, out=out)
+        if out is None:
+            out = torch.empty((sh.batch, sh.ncoils, sh.nk), dtype=torch.complex64, device=image.device)
+        _check(load().nufft_forward(ctypes.byref(sh), _ptr(image), _ptr(self.smaps), _ptr(out),
+                                    ctypes.byref(self.params), _ptr(self.ws), self.ws_bytes, _stream()),
+               "nufft_forward")
+        return out
+
+    def adjoint(self, data: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """x ~ F^H(data): [B, nc, nk] -> [B, ny, nx]."""
+        sh = self.shape
+        _need(data, torch.complex64, "data", (sh.batch, sh.ncoils, sh.nk))
+        if out is not None:
+            _need(out, torch.complex64, "out", (sh.batch, sh.ny, sh.nx))
+        _on_gpu(self.smaps.device, data=data, out=out)
+        if out is None:
+            out = torch.empty((sh.batch, sh.ny, sh.nx), dtype=torch.complex64, device=data.device)
+        _check(load().nufft_adjoint(ctypes.byref(sh), _ptr(data), _ptr(self.smaps), _ptr(out),
+                                    ctypes.byref(self.params), _ptr(self.ws), self.ws_bytes, _stream()),
+               "nufft_adjoint")
         return out
 
 

@@ -3,6 +3,7 @@
     python -m paper_2006_14080_amd.profile_driver [fp32|bf16x3|fp16x3] [repeats]
     python -m paper_2006_14080_amd.profile_driver vec SLICES
     python -m paper_2006_14080_amd.profile_driver shard PRECISION [repeats]
+    python -m paper_2006_14080_amd.profile_driver nufft [repeats]
 
 The first form calls nudft_forward and the adjoint (nudft_adjoint_prepared,
 tables prepared once, as inside a solve) at the 256x256 / 8-coil /
@@ -100,9 +101,39 @@ def shard_timings(prec: int, repeats: int, parts: int = 8):
     print("profile driver done", flush=True)
 
 
+def nufft_timings(repeats: int):
+    """NUFFT operator (width 6, oversampling 2) beside the dense NUDFT (FP32,
+    BF16x3) at the 256x256 / 8-coil / 64x512-sample and the 1024x512 /
+    12-coil / 101x1024-sample shapes: HIP-event times per call (plan and
+    phase tables built once, as inside a solve) and the NUFFT's plan time."""
+    g = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for wl in (synth.ADMM256, synth.TABLE1_1024x512):
+        img = g(synth.ellipse_phantom(wl.nx, wl.ny, wl.seed)[None])
+        sm = g(synth.coil_maps(wl.nx, wl.ny, wl.nc))
+        tr = g(synth.radial_trajectory(wl.n_spokes, wl.n_readout))
+        dat = g(synth.random_complex((1, wl.nc, wl.nk), 1))
+        y = torch.empty((1, wl.nc, wl.nk), dtype=torch.complex64, device="cuda")
+        x = torch.empty((1, wl.ny, wl.nx), dtype=torch.complex64, device="cuda")
+        shape = f"{wl.nx}x{wl.ny} c{wl.nc} nk={wl.nk}"
+        tp = _time_ms(lambda: mri.NufftPlan(sm, tr, wl.ny, wl.nx), 2)
+        plan = mri.NufftPlan(sm, tr, wl.ny, wl.nx)
+        tf = _time_ms(lambda: plan.forward(img, out=y), repeats)
+        ta = _time_ms(lambda: plan.adjoint(dat, out=x), repeats)
+        print(f"nufft   {shape}  fwd {tf:8.3f} ms  adj {ta:8.3f} ms  plan {tp:8.3f} ms", flush=True)
+        for prec in (mri.FP32, mri.BF16X3):
+            adj = mri.AdjointPlan(sm, tr, wl.ny, wl.nx, precision=prec)
+            tf = _time_ms(lambda: mri.nudft_forward(img, sm, tr, precision=prec, out=y), max(2, repeats // 4))
+            ta = _time_ms(lambda: adj(dat, out=x), max(2, repeats // 4))
+            print(f"{mri.PRECISION_NAMES[prec]:7s} {shape}  fwd {tf:8.3f} ms  adj {ta:8.3f} ms", flush=True)
+    print("profile driver done", flush=True)
+
+
 def main(argv):
     if len(argv) > 1 and argv[1] == "vec":
         vector_sweep(int(argv[2]))
+        return
+    if len(argv) > 1 and argv[1] == "nufft":
+        nufft_timings(int(argv[2]) if len(argv) > 2 else 20)
         return
     if len(argv) > 1 and argv[1] == "shard":
         shard_timings(mri.PRECISIONS[argv[2]], int(argv[3]) if len(argv) > 3 else 5)

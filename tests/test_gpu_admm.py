@@ -225,3 +225,45 @@ def test_slices384_batch_solve_against_stored_oracle(prec):
         print(f"{mri.PRECISION_NAMES[prec]}: 32x384^2 batch, slice {b}, {na}x{ncg}: image NRMSE vs stored "
               f"oracle {e:.3e}")
         assert e <= (NRMSE if prec != mri.BF16X3 else 1e-2)
+
+
+def _nufft_oracle_admm(data, smaps, traj, ny, nx, lam, beta, na, ncg):
+    """The oracle's ADMM with F applied by the oracle NUFFT (width 6,
+    oversampling 2): the reference of admm_solve's MRI_NUFFT mode."""
+    from oracle import nufft as onufft
+    from oracle import tv as otv
+    plan = onufft.Plan(nx, ny, traj, width=6, sigma=2.0)
+
+    def apply_a(v):
+        return onufft.adjoint(onufft.forward(v, smaps, plan), smaps, plan) + \
+            0.5 * beta * otv.tv_adjoint(otv.tv_forward(v))
+
+    return oadmm.admm(data, smaps, traj, lam, beta, na, ncg, apply_a=apply_a,
+                      adjoint=lambda u: onufft.adjoint(u, smaps, plan))
+
+
+@pytest.mark.parametrize("wl,na,ncg", [(synth.ADMM32, 10, 3), (synth.ADMM256, 2, 2)])
+def test_nufft_operator_solve(wl, na, ncg):
+    # admm_solve with the NUFFT operator against the oracle ADMM on the oracle
+    # NUFFT (1e-4 bar), and how far it lands from the dense-operator oracle
+    # solve (the operator's approximation, reported).
+    p = synth.make_problem(wl)
+    data = _data(p)
+    img, st = _solve(p, data, mri.AdmmParams(wl.lam, wl.beta, na, ncg, precision=mri.NUFFT))
+    ref = _nufft_oracle_admm(data[0], p.smaps, p.traj, wl.ny, wl.nx, wl.lam, wl.beta, na, ncg)
+    assert st[0]["status"] == 0 and st[0]["admm_iters"] == ref.admm_iters and st[0]["cg_steps"] == ref.cg_steps
+    e = nrmse(img[0], ref.image)
+    dense = _oracle(p, data, 0, wl.lam, wl.beta, na, ncg).image
+    print(f"nufft solve {wl.name} {na}x{ncg}: NRMSE vs oracle NUFFT solve {e:.3e}, vs dense oracle solve "
+          f"{nrmse(img[0], dense):.3e}")
+    assert e <= NRMSE
+
+
+def test_nufft_mode_rejected_where_unsupported():
+    from paper_2006_14080_amd import serve
+    with pytest.raises(mri.MriError):
+        serve.Server(1 << 26, max_slots=2, precision=mri.NUFFT)
+    wl = synth.ADMM32
+    p = synth.make_problem(wl)
+    with pytest.raises(mri.MriError):
+        mri.nudft_forward(_gpu(p.truth), _gpu(p.smaps), _gpu(p.traj), precision=mri.NUFFT)
