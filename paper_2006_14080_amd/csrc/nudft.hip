@@ -929,6 +929,11 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
     const int ncgroups = (nc + gsz - 1) / gsz;
     for (int gi = 0, g0 = 0; g0 < nc; ++gi, g0 += gsz) {
         const int ncg = min(gsz, nc - g0);
+        // The split's last sample, as a value the compiler takes as new in
+        // every coil group: indices derived from it are formed where they are
+        // used instead of being kept in registers across the group loop.
+        int kl = klast;
+        asm volatile("" : "+s"(kl));
         const int nvalid = max(0, min(nt, ncg - wm * nt));
         // Rows of coils past the group's end read coil g0 and feed only
         // accumulator tiles that the epilogue never reads.
@@ -946,13 +951,13 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
         // d of this thread's 4 K values of step s (clamped to the split's
         // last sample in the last step; those samples meet a zero E).
         auto load_d = [&](int s) {
-            if (s * KC + KC - 1 <= klast) {
+            if (s * KC + KC - 1 <= kl) {
                 const float2* p = drow + s * KC + 4 * ahalf;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) dreg[j] = p[j];
             } else {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) dreg[j] = drow[min(s * KC + 4 * ahalf + j, klast)];
+                for (int j = 0; j < 4; ++j) dreg[j] = drow[min(s * KC + 4 * ahalf + j, kl)];
             }
         };
         // Phases prefetched one step ahead (rows clamped to the split's last
@@ -961,18 +966,18 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
         float2 fx0, fx1, fy;
         auto load_fx = [&](int s) {
             const int k = s * KC + bk;
-            fx0 = phx[(int64_t)min(k, klast) * nx + xc];
-            fx1 = phx[(int64_t)min(k + 1, klast) * nx + xc];
+            fx0 = phx[(int64_t)min(k, kl) * nx + xc];
+            fx1 = phx[(int64_t)min(k + 1, kl) * nx + xc];
         };
-        auto load_fy = [&](int s) { fy = phy[(int64_t)min(s * KC + ek, klast) * ny + yc]; };
+        auto load_fy = [&](int s) { fy = phy[(int64_t)min(s * KC + ek, kl) * ny + yc]; };
         auto gen_e = [&](int st, int s) {
-            const float m = (ey_ok && s * KC + ek <= klast) ? 1.f : 0.f;
+            const float m = (ey_ok && s * KC + ek <= kl) ? 1.f : 0.f;
             sE[st][ey][ecol] = make_float2(fy.x * m, fy.y * m);
         };
         auto gen_b = [&](int st, int s) {
             const int k = s * KC + bk;
-            const float m0 = (bx_ok && k <= klast) ? 1.f : 0.f;
-            const float m1 = (bx_ok && k + 1 <= klast) ? 1.f : 0.f;
+            const float m0 = (bx_ok && k <= kl) ? 1.f : 0.f;
+            const float m1 = (bx_ok && k + 1 <= kl) ? 1.f : 0.f;
             P::template store_b<BC>(sB0 + st * kBBytes8, bx, bk, make_float2(fx0.x * m0, fx0.y * m0),
                                     make_float2(fx1.x * m1, fx1.y * m1));
         };
@@ -1043,18 +1048,18 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
                     for (int j = 0; j < 4; ++j) dreg[j] = q[j];
                 } else if (piece == 2) {          // conj(Ex) of step s+1: first value
                     const int k = (s + 1) * KC + bk;
-                    const float m0 = (bx_ok && k <= klast) ? 1.f : 0.f;
+                    const float m0 = (bx_ok && k <= kl) ? 1.f : 0.f;
                     r0 = P::split_b(make_float2(fx0.x * m0, fx0.y * m0));
                 } else if (piece == 3) {          // second value; store B(s+1); next phases
                     const int k = (s + 1) * KC + bk;
-                    const float m1 = (bx_ok && k + 1 <= klast) ? 1.f : 0.f;
+                    const float m1 = (bx_ok && k + 1 <= kl) ? 1.f : 0.f;
                     P::template store_b_words<BC>(sB0 + (cur ^ 1) * kBBytes8, bx, bk, r0,
                                                   P::split_b(make_float2(fx1.x * m1, fx1.y * m1)));
                     const float2* q = phx + (int64_t)((s + 2) * KC + bk) * nx + xc;
                     fx0 = q[0];
                     fx1 = q[nx];
                 } else if (piece == 4) {          // conj(Ey) of step s+2; fy(s+3)
-                    const float m = (ey_ok && (s + 2) * KC + ek <= klast) ? 1.f : 0.f;
+                    const float m = (ey_ok && (s + 2) * KC + ek <= kl) ? 1.f : 0.f;
                     sE[cur][ey][ecol] = make_float2(fy.x * m, fy.y * m);
                     load_fy(s + 3);
                 }

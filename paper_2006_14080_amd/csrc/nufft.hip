@@ -329,8 +329,9 @@ __global__ __launch_bounds__(kT) void k_nufft_spread(const NufftGeom g, const fl
         }
     }
     const int64_t gsz = (int64_t)g.gx * g.gy;
-    for (int c = 0; c < ncoil; ++c)
-        grid[((int64_t)b * g.nc + c0 + c) * gsz + (int64_t)gyi * g.gx + gxi] = acc[c];
+#pragma unroll
+    for (int c = 0; c < kSpreadCoils; ++c)      // constant indices keep acc in registers
+        if (c < ncoil) grid[((int64_t)b * g.nc + c0 + c) * gsz + (int64_t)gyi * g.gx + gxi] = acc[c];
 }
 
 // Adjoint step 3: crop, deapodise and combine the coils in a fixed order.
