@@ -402,18 +402,35 @@ __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
     const int64_t npix = (int64_t)it.nx * it.ny;
     const float2* im = it.img + b * npix + (int64_t)y * it.nx;
-    float2 xv[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) xv[j] = x0 + j < it.nx ? im[x0 + j] : make_float2(0.f, 0.f);
     const float2* sm = it.smaps + b * it.smaps_bs + (int64_t)y * it.nx;
+    // Four pixels as two 16-byte loads where the group lies inside the row and
+    // both arrays are 16-byte aligned there (every coil's map then is too,
+    // since a map has an even pixel count); one by one otherwise.
+    const bool wide = x0 + 3 < it.nx && (npix & 1) == 0 &&
+                      ((reinterpret_cast<uintptr_t>(im + x0) | reinterpret_cast<uintptr_t>(sm + x0)) & 15) == 0;
+    auto load4 = [&](const float2* p, float2 (&v)[4]) {
+        if (wide) {
+            const float4 lo = *reinterpret_cast<const float4*>(p + x0);
+            const float4 hi = *reinterpret_cast<const float4*>(p + x0 + 2);
+            v[0] = make_float2(lo.x, lo.y);
+            v[1] = make_float2(lo.z, lo.w);
+            v[2] = make_float2(hi.x, hi.y);
+            v[3] = make_float2(hi.z, hi.w);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = x0 + j < it.nx ? p[x0 + j] : make_float2(0.f, 0.f);
+        }
+    };
+    float2 xv[4];
+    load4(im, xv);
     float2* dst = it.wimg + ((int64_t)b * it.nc * it.ny + y) * rowlen + x0;
     const int64_t coil_stride = (int64_t)it.ny * rowlen;
 #pragma unroll 4
     for (int g = 0; g < it.nc; ++g) {
-        const float2* sg = sm + g * npix;
-        float2 v[4];
+        float2 sv[4], v[4];
+        load4(sm + g * npix, sv);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = x0 + j < it.nx ? cmul(sg[x0 + j], xv[j]) : make_float2(0.f, 0.f);
+        for (int j = 0; j < 4; ++j) v[j] = cmul(sv[j], xv[j]);   // zero past nx: xv is zero there
         float4* d4 = reinterpret_cast<float4*>(dst + g * coil_stride);
         d4[0] = make_float4(v[0].x, v[0].y, v[1].x, v[1].y);
         d4[1] = make_float4(v[2].x, v[2].y, v[3].x, v[3].y);
