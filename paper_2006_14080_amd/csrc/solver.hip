@@ -81,21 +81,10 @@ __device__ __forceinline__ void st_nt(float2* p, float2 v) {
 
 // Horizontal periodic neighbours.  The lanes of a wave hold 64 adjacent
 // columns of a row, so a value's left and right neighbours come from the
-// adjacent lanes (wave shuffles); only the first lane (left) and the last
-// lane or the image's last column (right) load theirs.  The edge loads are
-// issued with the thread's other loads (edge_left / edge_right, before any
-// use), so a wave makes one memory round trip; left_of / right_of then pick
-// the shuffled or the loaded value and must be called by every lane.
-__device__ __forceinline__ float2 edge_left(const float2* a, int row, int nx, const Tile& l) {
-    float2 v = make_float2(0.f, 0.f);
-    if (l.lane == 0) v = a[(int64_t)row * nx + (l.x == 0 ? nx - 1 : l.x - 1)];   // lane 0 always has x < nx
-    return v;
-}
-__device__ __forceinline__ float2 edge_right(const float2* a, int row, int nx, const Tile& l) {
-    float2 v = make_float2(0.f, 0.f);
-    if (l.lane == kTileX - 1 || l.x + 1 >= nx) v = a[(int64_t)row * nx + (l.x + 1 >= nx ? 0 : l.x + 1)];
-    return v;
-}
+// adjacent lanes (wave shuffles); the first lane (left) and the last lane or
+// the image's last column (right) take the edge values that wave_edges*
+// loads with the thread's other loads.  left_of / right_of pick the shuffled
+// or the edge value and must be called by every lane.
 __device__ __forceinline__ float2 left_of(const Tile& l, float2 c, float2 edge) {
     const float2 v = make_float2(__shfl_up(c.x, 1, 64), __shfl_up(c.y, 1, 64));
     return l.lane == 0 ? edge : v;
@@ -104,6 +93,63 @@ __device__ __forceinline__ float2 right_of(const Tile& l, int nx, float2 c, floa
     const float2 v = make_float2(__shfl_down(c.x, 1, 64), __shfl_down(c.y, 1, 64));
     return (l.lane == kTileX - 1 || l.x + 1 >= nx) ? edge : v;
 }
+
+// The edge columns of a wave's rows in one load instruction: lanes 0 .. R-1
+// load the left neighbours of the wave's first column in its rows 0 .. R-1,
+// lanes R .. 2R-1 the right neighbours of its last column (the column after
+// the tile, or column 0 when the image's last column lies in the tile); every
+// lane then receives all of them by shuffles, for left_of / right_of.
+__device__ __forceinline__ void wave_edges(const float2* a, const Tile& l, int nx, int ny,
+                                           float2 (&el)[kVecRows], float2 (&er)[kVecRows]) {
+    static_assert(2 * kVecRows <= kTileX, "edge lanes");
+    const int x0 = l.x - l.lane;
+    float2 v = make_float2(0.f, 0.f);
+    if (l.lane < 2 * kVecRows) {
+        const int j = l.lane % kVecRows;
+        const int col = l.lane < kVecRows ? (x0 == 0 ? nx - 1 : x0 - 1) : (x0 + kTileX < nx ? x0 + kTileX : 0);
+        v = a[(int64_t)load_row(l, j, ny) * nx + col];
+    }
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) {
+        el[j] = make_float2(__shfl(v.x, j, 64), __shfl(v.y, j, 64));
+        er[j] = make_float2(__shfl(v.x, kVecRows + j, 64), __shfl(v.y, kVecRows + j, 64));
+    }
+}
+// Only the left edges (lanes 0 .. R-1 load).
+__device__ __forceinline__ void wave_edges_left(const float2* a, const Tile& l, int nx, int ny,
+                                                float2 (&el)[kVecRows]) {
+    const int x0 = l.x - l.lane;
+    float2 v = make_float2(0.f, 0.f);
+    if (l.lane < kVecRows) v = a[(int64_t)load_row(l, l.lane, ny) * nx + (x0 == 0 ? nx - 1 : x0 - 1)];
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) el[j] = make_float2(__shfl(v.x, j, 64), __shfl(v.y, j, 64));
+}
+// Only the right edges (lanes 0 .. R-1 load).
+__device__ __forceinline__ void wave_edges_right(const float2* a, const Tile& l, int nx, int ny,
+                                                 float2 (&er)[kVecRows]) {
+    const int x0 = l.x - l.lane;
+    float2 v = make_float2(0.f, 0.f);
+    if (l.lane < kVecRows) v = a[(int64_t)load_row(l, l.lane, ny) * nx + (x0 + kTileX < nx ? x0 + kTileX : 0)];
+#pragma unroll
+    for (int j = 0; j < kVecRows; ++j) er[j] = make_float2(__shfl(v.x, j, 64), __shfl(v.y, j, 64));
+}
+
+// The block's row groups (one per wave, kVecRows rows each) pass rows to
+// their neighbours through LDS: the row above a group is the previous group's
+// last row and the row below is the next group's first row, so only the
+// first group loads the row above the tile and only the last group the row
+// below it.  Every thread of the block must call it.
+constexpr int kRowGroups = kVecThreads / kTileX;
+__device__ __forceinline__ void swap_rows(const Tile& l, float2 first, float2 last, float2& above, float2& below) {
+    __shared__ float2 s[2][kRowGroups][kTileX];
+    const int g = threadIdx.x / kTileX;
+    s[0][g][l.lane] = first;
+    s[1][g][l.lane] = last;
+    __syncthreads();
+    if (g > 0) above = s[1][g - 1][l.lane];
+    if (g < kRowGroups - 1) below = s[0][g + 1][l.lane];
+}
+__device__ __forceinline__ int row_group() { return threadIdx.x / kTileX; }
 
 __device__ __forceinline__ double cnorm2(float2 a) {
     return (double)a.x * a.x + (double)a.y * a.y;
@@ -184,16 +230,19 @@ __global__ __launch_bounds__(kVecThreads) void k_mu(const SolveTable tab) {
     const float2* eta = it.eta + (int64_t)l.b * 2 * it.npix;
     float2* mu = it.mu + (int64_t)l.b * 2 * it.npix;
     float2 r[kVecRows + 1], e0[kVecRows], e1[kVecRows], er[kVecRows];
+    wave_edges_right(rho, l, nx, ny, er);
 #pragma unroll
-    for (int j = 0; j < kVecRows; ++j) er[j] = edge_right(rho, load_row(l, j, ny), nx, l);
-#pragma unroll
-    for (int i = 0; i <= kVecRows; ++i) r[i] = rho[(int64_t)load_row(l, i, ny) * nx + xc];
+    for (int i = 0; i < kVecRows; ++i) r[i] = rho[(int64_t)load_row(l, i, ny) * nx + xc];
+    float2 unused = make_float2(0.f, 0.f);
+    r[kVecRows] = make_float2(0.f, 0.f);
+    if (row_group() == kRowGroups - 1) r[kVecRows] = rho[(int64_t)load_row(l, kVecRows, ny) * nx + xc];
 #pragma unroll
     for (int j = 0; j < kVecRows; ++j) {
         const int64_t pix = (int64_t)load_row(l, j, ny) * nx + xc;
         e0[j] = ld_nt(eta + pix);
         e1[j] = ld_nt(eta + it.npix + pix);
     }
+    swap_rows(l, r[0], r[kVecRows - 1], unused, r[kVecRows]);
     float2 rr[kVecRows];
 #pragma unroll
     for (int j = 0; j < kVecRows; ++j) rr[j] = right_of(l, nx, r[j], er[j]);
@@ -226,16 +275,13 @@ __global__ __launch_bounds__(kVecThreads) void k_rhs(const SolveTable tab) {
     const float2* et1 = et0 + it.npix;
     const int64_t base = (int64_t)l.b * it.npix;
     // g1 on the row above the band and the band's rows; g0 on the band's rows
-    float2 g1[kVecRows + 1], g0[kVecRows], fh[kVecRows], el[kVecRows];
+    float2 g1[kVecRows + 1], g0[kVecRows], fh[kVecRows], el[kVecRows], ml[kVecRows], tl[kVecRows];
+    wave_edges_left(mu0, l, nx, ny, ml);      // g0 at x - 1 for lane 0
+    wave_edges_left(et0, l, nx, ny, tl);
 #pragma unroll
-    for (int j = 0; j < kVecRows; ++j) {      // g0 at x - 1 for lane 0
-        el[j] = make_float2(0.f, 0.f);
-        if (l.lane == 0) {
-            const int64_t o = (int64_t)load_row(l, j, ny) * nx + (l.x == 0 ? nx - 1 : l.x - 1);
-            el[j] = csub(mu0[o], et0[o]);
-        }
-    }
-    {
+    for (int j = 0; j < kVecRows; ++j) el[j] = csub(ml[j], tl[j]);
+    g1[0] = make_float2(0.f, 0.f);
+    if (row_group() == 0) {
         const int64_t pa = (int64_t)row_above(l, ny) * nx + xc;
         g1[0] = csub(mu1[pa], et1[pa]);
     }
@@ -246,6 +292,8 @@ __global__ __launch_bounds__(kVecThreads) void k_rhs(const SolveTable tab) {
         g0[j] = csub(mu0[pix], et0[pix]);
         fh[j] = ld_nt(it.fhd + base + pix);
     }
+    float2 unused = make_float2(0.f, 0.f);
+    swap_rows(l, g1[1], g1[kVecRows], g1[0], unused);
     float2 gl[kVecRows];
 #pragma unroll
     for (int j = 0; j < kVecRows; ++j) gl[j] = left_of(l, g0[j], el[j]);
@@ -286,14 +334,12 @@ __global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab
     const float2* src = mode == kFinishCgStep ? it.p + base : (it.warm ? it.rho + base : it.rho0 + base);
     float2 c[kVecRows + 2], el[kVecRows], er[kVecRows], bv[kVecRows];
     if constexpr (mode != kFinishFhd) {
+        wave_edges(src, l, nx, ny, el, er);
+        c[0] = c[kVecRows + 1] = make_float2(0.f, 0.f);
+        if (row_group() == 0) c[0] = src[(int64_t)row_above(l, ny) * nx + xc];
 #pragma unroll
-        for (int j = 0; j < kVecRows; ++j) {
-            el[j] = edge_left(src, load_row(l, j, ny), nx, l);
-            er[j] = edge_right(src, load_row(l, j, ny), nx, l);
-        }
-        c[0] = src[(int64_t)row_above(l, ny) * nx + xc];
-#pragma unroll
-        for (int i = 0; i <= kVecRows; ++i) c[i + 1] = src[(int64_t)load_row(l, i, ny) * nx + xc];
+        for (int i = 0; i < kVecRows; ++i) c[i + 1] = src[(int64_t)load_row(l, i, ny) * nx + xc];
+        if (row_group() == kRowGroups - 1) c[kVecRows + 1] = src[(int64_t)load_row(l, kVecRows, ny) * nx + xc];
         if constexpr (mode == kFinishCgInit) {
 #pragma unroll
             for (int j = 0; j < kVecRows; ++j) bv[j] = ld_nt(it.b + base + pc[j]);
@@ -320,6 +366,7 @@ __global__ __launch_bounds__(kVecThreads) void k_adj_finish(const SolveTable tab
         for (int j = 0; j < kVecRows; ++j)
             if (row_ok(l, j, ny)) st_nt(it.fhd + base + pc[j], make_float2((float)sr[j], (float)si[j]));
     } else {
+        swap_rows(l, c[1], c[kVecRows], c[0], c[kVecRows + 1]);
         float2 q[kVecRows];
 #pragma unroll
         for (int j = 0; j < kVecRows; ++j) {
@@ -421,10 +468,11 @@ __global__ __launch_bounds__(kVecThreads) void k_dual(const SolveTable tab) {
     float2* eta = it.eta + 2 * base;
     const float2* mu = it.mu + 2 * base;
     float2 c[kVecRows + 1], e0[kVecRows], e1[kVecRows], m0[kVecRows], m1[kVecRows], old[kVecRows], er[kVecRows];
+    wave_edges_right(xn, l, nx, ny, er);
 #pragma unroll
-    for (int j = 0; j < kVecRows; ++j) er[j] = edge_right(xn, load_row(l, j, ny), nx, l);
-#pragma unroll
-    for (int i = 0; i <= kVecRows; ++i) c[i] = xn[(int64_t)load_row(l, i, ny) * nx + xc];
+    for (int i = 0; i < kVecRows; ++i) c[i] = xn[(int64_t)load_row(l, i, ny) * nx + xc];
+    c[kVecRows] = make_float2(0.f, 0.f);
+    if (row_group() == kRowGroups - 1) c[kVecRows] = xn[(int64_t)load_row(l, kVecRows, ny) * nx + xc];
 #pragma unroll
     for (int j = 0; j < kVecRows; ++j) {
         const int64_t pix = (int64_t)load_row(l, j, ny) * nx + xc;
@@ -434,6 +482,8 @@ __global__ __launch_bounds__(kVecThreads) void k_dual(const SolveTable tab) {
         m1[j] = ld_nt(mu + it.npix + pix);
         old[j] = ld_nt(it.rho + base + pix);
     }
+    float2 unused = make_float2(0.f, 0.f);
+    swap_rows(l, c[0], c[kVecRows - 1], unused, c[kVecRows]);
     float2 rr[kVecRows];
 #pragma unroll
     for (int j = 0; j < kVecRows; ++j) rr[j] = right_of(l, nx, c[j], er[j]);
