@@ -238,7 +238,7 @@ int nudft_adjoint_prepared(const mri_shape* shape, const mri_c32* y, const mri_c
     it.part = static_cast<float2*>(ws);
     adj_split(shape->nx, shape->ny, shape->ncoils, shape->nk, shape->batch, precision, &it.ksplit, &it.kper);
     bind_adj_tables(it, *shape, ws);
-    const NudftTable t = single_table(it, adj_tiles_per_split(shape->nx, shape->ny, shape->batch) * it.ksplit);
+    const NudftTable t = single_table(it, adj_tiles(shape->nx, shape->ny, shape->ncoils, shape->batch, it.ksplit));
     hipStream_t s = static_cast<hipStream_t>(stream);
     MRI_HIP(launch_nudft_adjoint(t, precision, s));
     MRI_HIP(launch_sum_partials(it.part, adj_partial_planes(shape->ncoils, it.ksplit),

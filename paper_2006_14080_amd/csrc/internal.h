@@ -65,6 +65,8 @@ int64_t fwd_tiles(int nx, int ny, int nc, int64_t nk, int nb);
 int64_t fwd_wimg_elems(int nx, int ny, int nc, int nb);
 // Adjoint tiles (workgroups) per sample split: nb x 128-column x 32-row blocks.
 int64_t adj_tiles_per_split(int nx, int ny, int nb);
+// Workgroups of one adjoint launch for a problem: pixel tiles x coil groups x sample splits.
+int64_t adj_tiles(int nx, int ny, int nc, int nb, int ksplit);
 // Row tiles per wave of the forward (by ny) and of the adjoint (by coil count).
 __host__ __device__ inline int fwd_nt(int ny) {
     const int npass = (ny + 255) / 256;
@@ -98,9 +100,9 @@ __host__ __device__ inline int adj_nt(int nc) {
     return nt < 2 ? 2 : nt;
 }
 // Partial images the adjoint writes per slice: one per (sample split, coil group).
-__host__ __device__ inline int adj_partial_planes(int nc, int ksplit) {
-    return ksplit * ((nc + 2 * adj_nt(nc) - 1) / (2 * adj_nt(nc)));
-}
+// Coil groups of the adjoint (one per workgroup and partial image).
+__host__ __device__ inline int adj_coil_groups(int nc) { return (nc + 2 * adj_nt(nc) - 1) / (2 * adj_nt(nc)); }
+__host__ __device__ inline int adj_partial_planes(int nc, int ksplit) { return ksplit * adj_coil_groups(nc); }
 // Adjoint workspace: the partial images [planes][nb][ny][nx], then (split-FP16
 // form) one int32 scale exponent per (slice, coil, sample split).
 __host__ __device__ inline int64_t adj_partial_elems(int nx, int ny, int nc, int nb, int ksplit) {

@@ -873,11 +873,11 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint: tile = (slice, sample split, 32 y rows, 128 x columns), 8 waves
-// (2 row x 4 column waves, one workgroup per CU).  GEMM rows are (coil, y)
-// for a group of 2 NT coils per pass: A = W = d conj(Ey), B = conj(Ex), K =
-// samples of the split; the epilogue forms sum_g conj(s_g) X_g and writes the
-// group's partial image for the fixed-order reduction.  The 128-column tile
+// Adjoint: tile = (slice, sample split, coil group, 32 y rows, 128 x
+// columns), 8 waves (2 row x 4 column waves, one workgroup per CU).  GEMM rows
+// are (coil, y) for the tile's group of 2 NT coils: A = W = d conj(Ey), B =
+// conj(Ex), K = samples of the split; the epilogue forms sum_g conj(s_g) X_g
+// and writes the (split, group) partial image for the fixed-order reduction.  The 128-column tile
 // lets every W value feed twice the MFMAs of a 64-column one, halving the
 // vector work of W per matrix instruction.  Each thread forms half a W row
 // (4 K values) and stages two conj(Ex) values and one conj(Ey) value per step
@@ -902,12 +902,17 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
     const NudftItem& it = tab.it[find_item(tab, tile)];
     const int nx = it.nx, ny = it.ny, nc = it.nc;
     const int64_t nk = it.nk;
-    int local = tile - it.tile_begin;          // y blocks fastest, then x blocks, then splits
+    // y blocks fastest, then x blocks, then coil groups, then sample splits
+    constexpr int gsz = 2 * NT;
+    const int ncgroups = (nc + gsz - 1) / gsz;
+    int local = tile - it.tile_begin;
     const int nxb = (nx + BC - 1) / BC, nyb = (ny + kAdjRows - 1) / kAdjRows;
     const int yb = local % nyb;
     local /= nyb;
     const int xb = local % nxb;
     local /= nxb;
+    const int gi = local % ncgroups;
+    local /= ncgroups;
     const int sp = local % it.ksplit;
     const int b = local / it.ksplit;
     if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
@@ -942,15 +947,10 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
     const int xe = x0 + wn * 32 + l32;                   // epilogue column
 
     constexpr int nt = NT;
-    constexpr int gsz = 2 * NT;
-    const int ncgroups = (nc + gsz - 1) / gsz;
-    for (int gi = 0, g0 = 0; g0 < nc; ++gi, g0 += gsz) {
+    {
+        const int g0 = gi * gsz;                         // this workgroup's coil group
         const int ncg = min(gsz, nc - g0);
-        // The split's last sample, as a value the compiler takes as new in
-        // every coil group: indices derived from it are formed where they are
-        // used instead of being kept in registers across the group loop.
-        int kl = klast;
-        asm volatile("" : "+s"(kl));
+        const int kl = klast;
         const int nvalid = max(0, min(nt, ncg - wm * nt));
         // Rows of coils past the group's end read coil g0 and feed only
         // accumulator tiles that the epilogue never reads.
@@ -1157,30 +1157,49 @@ int64_t adj_tiles_per_split(int nx, int ny, int nb) {
     return (int64_t)nb * ceil_div(nx, kAdjCols) * ceil_div(ny, kAdjRows);
 }
 
+int64_t adj_tiles(int nx, int ny, int nc, int nb, int ksplit) {
+    return adj_tiles_per_split(nx, ny, nb) * adj_coil_groups(nc) * ksplit;
+}
+
 void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
                int32_t* ksplit, int32_t* kper) {
     // The split depends on the slice shape only (not on nb or on other
     // problems in a grouped launch), so every slice is summed in the same
     // order alone and in a batch: results are batch-invariant bit for bit.
-    (void)nc; (void)precision; (void)nb;
-    const int64_t tps = adj_tiles_per_split(nx, ny, 1);
-    // Splits: target / (128 x 32 pixel tiles of a slice), e.g. at 256^2 16
-    // sample ranges (2048 samples each at 8 coils): 256 workgroups of the
-    // adjoint tile, one per CU.  Twice as many (1024 samples each)
-    // ran the adjoint 1.7 % (FP32) to 5.5 % (split forms) slower: each
-    // workgroup's first steps, coil combine and partial image count twice;
-    // the longer FP32 accumulations raise the adjoint's error by about the
-    // square root of 2 (1.1e-6 vs the oracle in FP32 at 256^2).
-    const int64_t target = 256;
-    int64_t s = ceil_div(target, tps);
-    // At least 256 samples per split: short sample ranges (one GPU's share of
+    (void)precision; (void)nb;
+    // Workgroups per sample range: 128 x 32 pixel tiles times coil groups.
+    const int64_t per_split = adj_tiles_per_split(nx, ny, 1) * adj_coil_groups(nc);
+    // At least 256 samples per range: short sample ranges (one GPU's share of
     // a k-space split, 4096 samples per coil at 256^2) then still fill the
     // GPU; 512 left half of it idle there (adjoint 9 % slower in FP32, 30 %
     // in the split forms), and 128 spends more on each workgroup's coil
-    // combine and on the partial images than it gains.
+    // combine and on the partial images than it gains.  At most 65536
+    // samples per range, which bounds the length of the FP32 accumulations.
     const int64_t smax = std::max<int64_t>(1, nk / 256);
-    if (s > smax) s = smax;
-    if (s < 1) s = 1;
+    const int64_t smin = std::min<int64_t>(smax, ceil_div(nk, 65536));
+    // The fewest ranges whose workgroups fill whole rounds of the 256 CUs to
+    // at least 90 % (one workgroup per CU): e.g. 16 ranges of 2048 samples at
+    // 256^2 with 8 coils (256 workgroups), 5 at 384^2 with 32 coils (720
+    // workgroups in three rounds, where 8 ranges, 288 workgroups, left the
+    // second round almost empty and ran the adjoint at 56 % of the forward's
+    // rate).  A problem too small to fill one round takes the most ranges;
+    // one that never reaches 90 % takes the best-filled count.
+    constexpr int64_t kCUs = 256;
+    int64_t s = -1, best = smin;
+    double best_fill = 0.0;
+    for (int64_t c = smin; c <= smax && c <= 4 * kCUs; ++c) {
+        const int64_t w = c * per_split, rounds = ceil_div(w, kCUs);
+        const double fill = (double)w / (double)(rounds * kCUs);
+        if (w >= kCUs && fill >= 0.9) {
+            s = c;
+            break;
+        }
+        if (fill > best_fill + 1e-9) {
+            best_fill = fill;
+            best = c;
+        }
+    }
+    if (s < 0) s = smax * per_split < kCUs ? smax : best;
     int64_t per = ceil_div(ceil_div(nk, s), KC) * KC;
     s = ceil_div(nk, per);
     *ksplit = (int32_t)s;
@@ -1255,9 +1274,7 @@ hipError_t adj8_variant(const NudftTable& t, int nt, hipStream_t s) {
 }
 
 // Tiles of the adjoint: (slice, 32 y, 128 x, sample split).
-int64_t adj8_tiles(const NudftItem& it) {
-    return adj_tiles_per_split(it.nx, it.ny, it.nb) * it.ksplit;
-}
+int64_t adj8_tiles(const NudftItem& it) { return adj_tiles(it.nx, it.ny, it.nc, it.nb, it.ksplit); }
 
 }  // namespace
 

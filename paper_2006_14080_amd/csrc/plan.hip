@@ -212,7 +212,7 @@ int build_plan(const SolveBinding* bind, int n, int precision, Plan* out) {
         bind_adj_tables(base, sh, at<char>(ws, L.part));
         base.active_stride = (int32_t)(sizeof(SolveScalars) / sizeof(int32_t));
         const int64_t ft = fwd_tiles(sh.nx, sh.ny, sh.ncoils, sh.nk, sh.batch);
-        const int64_t at_ = adj_tiles_per_split(sh.nx, sh.ny, sh.batch) * L.ksplit;
+        const int64_t at_ = adj_tiles(sh.nx, sh.ny, sh.ncoils, sh.batch, L.ksplit);
         const int64_t cw = fwd_wimg_elems(sh.nx, sh.ny, sh.ncoils, sh.batch);
         if (cw >= ((int64_t)1 << 31) || fwd_split_units(sh.nx, sh.ny, sh.ncoils, sh.batch) >= ((int64_t)1 << 31))
             return MRI_ENOTSUP;     // 32-bit indexing inside an item
