@@ -84,3 +84,27 @@ def test_derived_bars():
     assert s["table1_128x64"]["c64"] > 10 * 1e-4
     assert bars.TABLE1_128x64 >= 2.0 * s["table1_128x64"]["c64"]
     assert s["table1_128x64"]["admm_iters"] == 5 and s["table1_128x64"]["cg_steps"] == 100
+
+
+
+def test_derived_bars_of_the_stored_problems():
+    # The BF16x3 bars of the three large problems: twice the largest shift of
+    # the oracle image at BF16x3's operator error, measured from the stored
+    # oracle reconstruction at that reconstruction's own iteration counts.
+    s = bars.SENSITIVITY
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    for key, bar, golden, counts in [
+            ("admm256_bf16x3", bars.BF16X3_ADMM256, "admm256_oracle.npz", lambda g: (30, 5)),
+            ("slices384_bf16x3", bars.BF16X3_SLICES384, "slices384_oracle.npz",
+             lambda g: (int(g["admm_iters"]), int(g["cg_iters"]))),
+            ("table1_large_bf16x3", bars.BF16X3_TABLE1_LARGE, "table1_large_oracle.npz",
+             lambda g: (int(g["admm_max"]), int(g["cg_max"])))]:
+        c = s[key]
+        shifts = c["noise"]["4e-06"]
+        assert len(shifts) >= 3 and min(shifts) > 0.0
+        assert bar == pytest.approx(2.0 * max(shifts))
+        assert c["reference"].startswith(golden)
+        assert tuple(c["counts"]) == counts(np.load(os.path.join(here, golden)))
+        # independent seeds land close together: the shift measures the
+        # solve's amplification, not one draw
+        assert max(shifts) <= 1.5 * min(shifts)
