@@ -171,8 +171,7 @@ struct PolSplit {
         uint32_t hi, lo;
     };
     __device__ __forceinline__ static Words split2(float a, float b) {
-        const vec2 h = {static_cast<T>(a), static_cast<T>(b)};
-        uint32_t hw = __builtin_bit_cast(uint32_t, h);
+        uint32_t hw, lw;
         float ha, hb;
         if constexpr (__is_same(T, __bf16)) {
             // A bf16 is the top half of an FP32: read both back from the packed
@@ -182,12 +181,18 @@ struct PolSplit {
             asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(hw) : "v"(a), "v"(b));
             ha = __builtin_bit_cast(float, hw << 16);
             hb = __builtin_bit_cast(float, hw & 0xffff0000u);
+            const vec2 l = {static_cast<T>(a - ha), static_cast<T>(b - hb)};
+            lw = __builtin_bit_cast(uint32_t, l);
         } else {
+            // Both halves in one packed conversion (round to nearest even, as
+            // the per-component conversion), for the high and the low parts.
+            asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(hw) : "v"(a), "v"(b));
+            const vec2 h = __builtin_bit_cast(vec2, hw);
             ha = static_cast<float>(h.x);
             hb = static_cast<float>(h.y);
+            asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(lw) : "v"(a - ha), "v"(b - hb));
         }
-        const vec2 l = {static_cast<T>(a - ha), static_cast<T>(b - hb)};
-        return {hw, __builtin_bit_cast(uint32_t, l)};
+        return {hw, lw};
     }
     // [x, y] -> [-y, x] on the two 16-bit halves (swap, then negate the low half).
     __device__ __forceinline__ static uint32_t rot(uint32_t w) {
@@ -224,8 +229,9 @@ struct PolSplit {
     __device__ __forceinline__ static void store_b(char* st, int col, int kp, float2 e0, float2 e1) {
         store_b_words<BC>(st, col, kp, split_b(e0), split_b(e1));
     }
-    // [Br, -Bi] words of one B value (phases carry the kBScale factor).
-    __device__ __forceinline__ static Words split_b(float2 e) { return split2(e.x * kBScale, -e.y * kBScale); }
+    // [Br, -Bi] words of one B value; the caller passes the phase already
+    // multiplied by kBScale (folded into a mask or a per-thread factor).
+    __device__ __forceinline__ static Words split_b(float2 e) { return split2(e.x, -e.y); }
     // B stages hold BC columns: [var][h][part][col], 16 bytes per chunk.
     template <int BC>
     __device__ __forceinline__ static void store_b_words(char* st, int col, int kp, Words r0, Words r1) {
@@ -644,8 +650,9 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
     const int pc = tid & 63, pj = (tid >> 6) * 2;
     const bool p_ok = k0 + pc < nk;
     const double fx4 = p_ok ? traj[2 * (k0 + pc)] * kQuarterTurnsPerRad : 0.0;
-    const float2 w0 = phase_neg(fx4, (double)pj);
-    const float2 w1 = phase_neg(fx4, (double)(pj + 1));
+    // (w0, w1 carry the B scale of the split forms: exact, a power of two)
+    const float2 w0 = cscale(phase_neg(fx4, (double)pj), P::kBScale);
+    const float2 w1 = cscale(phase_neg(fx4, (double)(pj + 1)), P::kBScale);
     const float2 wk = phase_neg(fx4, (double)KC);      // one K-step
     // Epilogue: this lane's sample column.
     const int64_t ke = k0 + wn * 32 + l32;
@@ -993,8 +1000,8 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
         };
         auto gen_b = [&](int st, int s) {
             const int k = s * KC + bk;
-            const float m0 = (bx_ok && k <= kl) ? 1.f : 0.f;
-            const float m1 = (bx_ok && k + 1 <= kl) ? 1.f : 0.f;
+            const float m0 = (bx_ok && k <= kl) ? P::kBScale : 0.f;     // mask and B scale
+            const float m1 = (bx_ok && k + 1 <= kl) ? P::kBScale : 0.f;
             P::template store_b<BC>(sB0 + st * kBBytes8, bx, bk, make_float2(fx0.x * m0, fx0.y * m0),
                                     make_float2(fx1.x * m1, fx1.y * m1));
         };
@@ -1065,11 +1072,11 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
                     for (int j = 0; j < 4; ++j) dreg[j] = q[j];
                 } else if (piece == 2) {          // conj(Ex) of step s+1: first value
                     const int k = (s + 1) * KC + bk;
-                    const float m0 = (bx_ok && k <= kl) ? 1.f : 0.f;
+                    const float m0 = (bx_ok && k <= kl) ? P::kBScale : 0.f;
                     r0 = P::split_b(make_float2(fx0.x * m0, fx0.y * m0));
                 } else if (piece == 3) {          // second value; store B(s+1); next phases
                     const int k = (s + 1) * KC + bk;
-                    const float m1 = (bx_ok && k + 1 <= kl) ? 1.f : 0.f;
+                    const float m1 = (bx_ok && k + 1 <= kl) ? P::kBScale : 0.f;
                     P::template store_b_words<BC>(sB0 + (cur ^ 1) * kBBytes8, bx, bk, r0,
                                                   P::split_b(make_float2(fx1.x * m1, fx1.y * m1)));
                     const float2* q = phx + (int64_t)((s + 2) * KC + bk) * nx + xc;
