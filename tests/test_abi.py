@@ -58,6 +58,35 @@ def test_adjoint_split(lib):
     assert lib.mri_adjoint_split(ctypes.byref(mri.make_shape(0, 8, 1, 8)), None, None, None) == -1
 
 
+def _workgroups(nx, ny, sp):
+    # 128 x 32 pixel tiles x (coil group, sample range) partial images
+    return -(-nx // 128) * -(-ny // 32) * sp["planes"]
+
+
+@pytest.mark.parametrize("nx,ny,nc,nk,ksplit", [
+    (256, 256, 8, 32768, 16),      # 256 workgroups, one round of the 256 CUs
+    (384, 384, 32, 98304, 5),      # 720 workgroups in three rounds (94 %); 8 ranges left a round near empty
+    (384, 384, 16, 98304, 7),      # 504 workgroups (98 %)
+    (128, 128, 32, 32768, 16),     # 4 coil groups x 4 tiles x 16 ranges
+    (1024, 512, 12, 103424, 2),    # at most 65536 samples per range
+    (256, 256, 8, 4096, 16),       # one GPU's share of an 8-way k-space split
+])
+def test_adjoint_split_fills_the_cus(nx, ny, nc, nk, ksplit):
+    sp = mri.adjoint_split(mri.make_shape(nx, ny, nc, nk))
+    assert sp["ksplit"] == ksplit
+    assert 256 <= sp["kper"] <= 65536 and sp["kper"] % 8 == 0
+    assert sp["ksplit"] * sp["kper"] >= nk > (sp["ksplit"] - 1) * sp["kper"]
+    w = _workgroups(nx, ny, sp)
+    assert w >= 256 and w / (-(-w // 256) * 256) >= 0.9
+
+
+def test_adjoint_split_of_small_problems_takes_the_most_ranges():
+    # a problem that cannot fill one round of the CUs: as many ranges as the
+    # 256-sample minimum allows
+    sp = mri.adjoint_split(mri.make_shape(128, 128, 4, 8192))
+    assert sp["ksplit"] == 8192 // 256 and _workgroups(128, 128, sp) < 256
+
+
 def test_strerror(lib):
     assert lib.mri_strerror(0) == b"success"
     assert b"invalid" in lib.mri_strerror(-1)
