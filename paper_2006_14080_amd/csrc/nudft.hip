@@ -339,21 +339,17 @@ struct PolSplit {
                     acc_im[t] = mfma(av, part == 2 ? bl[1] : bh[1], acc_im[t]);
                 }
             }
-            if constexpr (!kByTile) {
-                // The producer piece is scheduled among this group's matrix
-                // instructions: one MFMA, then up to five vector or scalar ALU
-                // instructions, so the SIMD issues them while the MFMAs run
-                // (forward 6 % faster; the adjoint's pieces wait on LDS reads
-                // and gained nothing, so there each piece follows its group).
-                prod(g);
+            // The producer piece is scheduled among this group's matrix
+            // instructions: one MFMA, then up to five vector or scalar ALU
+            // instructions, so the SIMD issues them while the MFMAs run
+            // (forward 6 % faster; adjoint 2-4 % faster once its pieces no
+            // longer read LDS, the conj(Ey) values being read at the start of
+            // the step).
+            prod(g);
 #pragma unroll
-                for (int q = 0; q < NT; ++q) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x006, 5, 0);   // five VALU / SALU
-                }
-            } else {
-                __builtin_amdgcn_sched_barrier(0);
-                prod(g);
+            for (int q = 0; q < NT; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x006, 5, 0);   // five VALU / SALU
             }
             __builtin_amdgcn_sched_barrier(0);
         }
@@ -1053,17 +1049,29 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
             const int cur = s & 1;
             float2 w[4];
             typename P::Words r0;
+            // conj(Ey)(s+1) of this thread's W row, complete since the last
+            // barrier: read before this step's products so that the
+            // producer pieces do not wait for LDS.
+            float2 ereg[4];
+            {
+                const float4 e01 = *reinterpret_cast<const float4*>(&sE[cur ^ 1][ay][4 * ahalf]);
+                const float4 e23 = *reinterpret_cast<const float4*>(&sE[cur ^ 1][ay][4 * ahalf + 2]);
+                ereg[0] = make_float2(e01.x, e01.y);
+                ereg[1] = make_float2(e01.z, e01.w);
+                ereg[2] = make_float2(e23.x, e23.y);
+                ereg[3] = make_float2(e23.z, e23.w);
+            }
             auto prod = [&](int piece) {
                 if (piece == 0) {                 // W(s+1), first two values
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
-                        w[j] = cmul(dreg[j], sE[cur ^ 1][ay][4 * ahalf + j]);
+                        w[j] = cmul(dreg[j], ereg[j]);
                         if constexpr (P::kScaled) w[j] = cscale(w[j], ascale);
                     }
                 } else if (piece == 1) {          // W(s+1), last two values; store; d(s+2)
 #pragma unroll
                     for (int j = 2; j < 4; ++j) {
-                        w[j] = cmul(dreg[j], sE[cur ^ 1][ay][4 * ahalf + j]);
+                        w[j] = cmul(dreg[j], ereg[j]);
                         if constexpr (P::kScaled) w[j] = cscale(w[j], ascale);
                     }
                     P::store_a_half(sA0 + (cur ^ 1) * P::kABytes, ac * 32 + ay, kRows, ahalf, w);
