@@ -385,15 +385,21 @@ __device__ __forceinline__ int split_scale_exp(float m) {
 // (the pitch is a multiple of 8, so a group never crosses a row), reads the
 // image once and writes the group for every coil (two 16-byte writes each).
 __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
-    int64_t gq = (int64_t)blockIdx.x * 256 + threadIdx.x;   // index of a 4-pixel group
+    // Each item starts on a block boundary, so the item (and every field read
+    // from it) is uniform over the block.
+    int64_t blk = blockIdx.x;
     int k = 0;
+    int64_t n = 0;
     for (; k < tab.nitems; ++k) {
         const NudftItem& c = tab.it[k];
-        const int64_t n = (int64_t)c.nb * c.ny * (ceil_div(c.nx, KC) * KC / 4);
-        if (gq < n) break;
-        gq -= n;
+        n = (int64_t)c.nb * c.ny * (ceil_div(c.nx, KC) * KC / 4);
+        const int64_t nblk = ceil_div(n, 256);
+        if (blk < nblk) break;
+        blk -= nblk;
     }
     if (k >= tab.nitems) return;
+    const int64_t gq = blk * 256 + threadIdx.x;   // index of a 4-pixel group within the item
+    if (gq >= n) return;
     const NudftItem& it = tab.it[k];
     const int rowlen = (int)ceil_div(it.nx, KC) * KC;
     const int gpr = rowlen / 4;                           // groups per padded row
@@ -401,7 +407,6 @@ __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
     const int b = i / (gpr * it.ny);
     const int rem = i - b * gpr * it.ny;
     const int y = rem / gpr, x0 = (rem - y * gpr) * 4;
-    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
     const int64_t npix = (int64_t)it.nx * it.ny;
     const float2* im = it.img + b * npix + (int64_t)y * it.nx;
     const float2* sm = it.smaps + b * it.smaps_bs + (int64_t)y * it.nx;
@@ -425,6 +430,9 @@ __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
     };
     float2 xv[4];
     load4(im, xv);
+    // The activity flag is read after the image loads are issued (the image
+    // of an inactive slice is still a valid buffer), so the two loads overlap.
+    if (it.active && it.active[(int64_t)b * it.active_stride] == 0) return;
     float2* dst = it.wimg + ((int64_t)b * it.nc * it.ny + y) * rowlen + x0;
     const int64_t coil_stride = (int64_t)it.ny * rowlen;
 #pragma unroll 4
@@ -444,20 +452,24 @@ __global__ __launch_bounds__(256) void k_coil_weight(const NudftTable tab) {
 // tile of the forward only copies 16-byte chunks.  Layout per (slice, coil):
 // [K-step s][chunk (h, m)][row y < yp][16 B], rows past ny are zero.
 __global__ __launch_bounds__(256) void k_coil_weight_bf16(const NudftTable tab) {
-    const int64_t gu = (int64_t)blockIdx.x * 256 + threadIdx.x;   // one (slice, coil, step, row) unit
+    // Each item starts on a block boundary (item uniform over the block).
+    int64_t blk = blockIdx.x;
     int k = 0;
-    int64_t begin = 0;
+    int64_t u = 0;
     for (; k < tab.nitems; ++k) {
         const NudftItem& c = tab.it[k];
-        const int64_t u = fwd_split_units(c.nx, c.ny, c.nc, c.nb);
-        if (gu < begin + u) break;
-        begin += u;
+        u = fwd_split_units(c.nx, c.ny, c.nc, c.nb);
+        const int64_t nblk = ceil_div(u, 256);
+        if (blk < nblk) break;
+        blk -= nblk;
     }
     if (k >= tab.nitems) return;
+    const int64_t gu = blk * 256 + threadIdx.x;   // one (slice, coil, step, row) unit of the item
+    if (gu >= u) return;
     const NudftItem& it = tab.it[k];
     const int yp = fwd_padded_rows(it.ny);
     const int nsteps = (int)ceil_div(it.nx, KC);
-    const int i = (int)(gu - begin);
+    const int i = (int)gu;
     const int y = i % yp;
     const int r1 = i / yp;
     const int s = r1 % nsteps;
@@ -484,21 +496,25 @@ __global__ __launch_bounds__(256) void k_coil_weight_bf16(const NudftTable tab) 
 // packs it as k_coil_weight_bf16 does.  The inverse scale of each row is kept
 // after the operand chunks (fwd_rowscale) for the forward's epilogue.
 __global__ __launch_bounds__(256) void k_coil_weight_f16(const NudftTable tab) {
-    const int64_t gr = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);   // one (slice, coil, row) unit
     const int lane = threadIdx.x & 63;
+    // Each item starts on a block boundary (item uniform over the block).
+    int64_t blk = blockIdx.x;
     int k = 0;
-    int64_t begin = 0;
+    int64_t u = 0;
     for (; k < tab.nitems; ++k) {
         const NudftItem& c = tab.it[k];
-        const int64_t u = (int64_t)c.nb * c.nc * fwd_padded_rows(c.ny);
-        if (gr < begin + u) break;
-        begin += u;
+        u = (int64_t)c.nb * c.nc * fwd_padded_rows(c.ny);
+        const int64_t nblk = ceil_div(u, 4);
+        if (blk < nblk) break;
+        blk -= nblk;
     }
     if (k >= tab.nitems) return;
+    const int64_t gr = blk * 4 + (threadIdx.x >> 6);   // one (slice, coil, row) unit of the item
+    if (gr >= u) return;
     const NudftItem& it = tab.it[k];
     const int yp = fwd_padded_rows(it.ny);
     const int nsteps = (int)ceil_div(it.nx, KC);
-    const int i = (int)(gr - begin);
+    const int i = (int)gr;
     const int y = i % yp;
     const int bg = i / yp;
     const int g = bg % it.nc, b = bg / it.nc;
@@ -1224,22 +1240,22 @@ void adj_split(int nx, int ny, int nc, int64_t nk, int nb, int precision,
 hipError_t launch_coil_weight(const NudftTable& t, int precision, hipStream_t s) {
     if (t.cw_total <= 0) return hipSuccess;
     if (precision == MRI_BF16X3) {
-        int64_t units = 0;
+        int64_t blocks = 0;
         for (int i = 0; i < t.nitems; ++i)
-            units += fwd_split_units(t.it[i].nx, t.it[i].ny, t.it[i].nc, t.it[i].nb);
-        hipLaunchKernelGGL(k_coil_weight_bf16, dim3((unsigned)ceil_div(units, 256)), dim3(256), 0, s, t);
+            blocks += ceil_div(fwd_split_units(t.it[i].nx, t.it[i].ny, t.it[i].nc, t.it[i].nb), 256);
+        hipLaunchKernelGGL(k_coil_weight_bf16, dim3((unsigned)blocks), dim3(256), 0, s, t);
         return hipGetLastError();
     }
     if (precision == MRI_FP16X3) {
-        int64_t rows = 0;
-        for (int i = 0; i < t.nitems; ++i) rows += fwd_rowscale_floats(t.it[i].ny, t.it[i].nc, t.it[i].nb);
-        hipLaunchKernelGGL(k_coil_weight_f16, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, s, t);
+        int64_t blocks = 0;
+        for (int i = 0; i < t.nitems; ++i) blocks += ceil_div(fwd_rowscale_floats(t.it[i].ny, t.it[i].nc, t.it[i].nb), 4);
+        hipLaunchKernelGGL(k_coil_weight_f16, dim3((unsigned)blocks), dim3(256), 0, s, t);
         return hipGetLastError();
     }
-    int64_t groups = 0;
+    int64_t blocks = 0;
     for (int i = 0; i < t.nitems; ++i)
-        groups += (int64_t)t.it[i].nb * t.it[i].ny * (ceil_div(t.it[i].nx, KC) * KC / 4);
-    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)ceil_div(groups, 256)), dim3(256), 0, s, t);
+        blocks += ceil_div((int64_t)t.it[i].nb * t.it[i].ny * (ceil_div(t.it[i].nx, KC) * KC / 4), 256);
+    hipLaunchKernelGGL(k_coil_weight, dim3((unsigned)blocks), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 
