@@ -7,6 +7,7 @@
                                            [--fetch <FETCH_SIZE csv> --write <WRITE_SIZE csv>]
     python -m paper_2006_14080_amd.profsum busy <run_kernel_trace.csv> --cmd "<command>"
     python -m paper_2006_14080_amd.profsum grid <run_kernel_trace.csv> --cmd "<command>"
+    python -m paper_2006_14080_amd.profsum clock <counter_collection.csv> --cmd "<command>"
 
 ``vecbw`` turns the durations of the solver's memory-bound kernels into
 achieved bandwidth from their algorithmic bytes per pixel (listed in
@@ -224,6 +225,42 @@ def kernel_fingerprint() -> str:
     return h.hexdigest()
 
 
+XCDS = 8                 # GRBM_GUI_ACTIVE is summed over the part's accelerator dies
+SIMDS = 256 * 4
+PEAK_CLOCK_GHZ = 2.4
+
+
+def clock(path):
+    """Per NUDFT dispatch: duration, shader clock (GRBM_GUI_ACTIVE per die over
+    the duration) and matrix-core busy cycles as a fraction of the SIMD cycles
+    at the peak clock and at the measured one; dispatches grouped into
+    quartiles of their duration."""
+    rows = list(csv.DictReader(open(path)))
+    d = collections.defaultdict(dict)
+    for r in rows:
+        k = short(r["Kernel_Name"])
+        if "nudft_" not in k:
+            continue
+        e = d[k].setdefault(r["Dispatch_Id"], {"us": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3})
+        e[r["Counter_Name"]] = e.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    out = []
+    for k, disp in d.items():
+        xs = sorted(disp.values(), key=lambda e: e["us"])
+        out.append(f"{k}: {len(xs)} dispatches")
+        out.append("  duration quartile   avg_us   clock_GHz   MFMA busy / SIMD cycles at 2.4 GHz   at the measured clock")
+        q = max(1, len(xs) // 4)
+        for i in range(4):
+            part = xs[i * q:(i + 1) * q] if i < 3 else xs[3 * q:]
+            if not part:
+                continue
+            us = sum(e["us"] for e in part) / len(part)
+            ghz = sum(e["GRBM_GUI_ACTIVE"] / XCDS / (e["us"] * 1e3) for e in part) / len(part)
+            f_peak = sum(e["SQ_VALU_MFMA_BUSY_CYCLES"] / (SIMDS * PEAK_CLOCK_GHZ * e["us"] * 1e3) for e in part) / len(part)
+            f_clk = sum(e["SQ_VALU_MFMA_BUSY_CYCLES"] / (SIMDS * e["GRBM_GUI_ACTIVE"] / XCDS) for e in part) / len(part)
+            out.append(f"  Q{i + 1:<17d} {us:8.1f}   {ghz:9.3f}   {f_peak:33.3f}   {f_clk:21.3f}")
+    return out
+
+
 def traffic(fetch_csv, write_csv):
     """HBM bytes per dispatch, each counter scaled by its reading for the copy."""
     f = _per_kernel(fetch_csv, "FETCH_SIZE")
@@ -287,7 +324,7 @@ def grid(trace_csv):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "pmc", "traffic", "vecbw", "busy", "grid"])
+    ap.add_argument("mode", choices=["stats", "pmc", "traffic", "vecbw", "busy", "grid", "clock"])
     ap.add_argument("csv")
     ap.add_argument("csv2", nargs="?")
     ap.add_argument("--cmd", required=True)
@@ -329,6 +366,14 @@ def main():
                 json.dump(d, fh, indent=1, sort_keys=True)
         for k, v in t.items():
             print(k, v)
+        return 0
+    if a.mode == "clock":
+        print("# NUDFT dispatches of a run: duration, shader clock and matrix-core busy fraction")
+        print(f"# command: {a.cmd}")
+        print(f"# clock = GRBM_GUI_ACTIVE / {XCDS} dies / duration; busy fraction = SQ_VALU_MFMA_BUSY_CYCLES over "
+              f"{SIMDS} SIMDs x cycles")
+        for line in clock(a.csv):
+            print(line)
         return 0
     if a.mode == "grid":
         print("# NUDFT kernels per launch shape from a rocprofv3 kernel trace")
