@@ -225,9 +225,8 @@ def kernel_fingerprint() -> str:
     return h.hexdigest()
 
 
-XCDS = 8                 # GRBM_GUI_ACTIVE is summed over the part's accelerator dies
-SIMDS = 256 * 4
-PEAK_CLOCK_GHZ = 2.4
+SIMDS = CUS * 4
+PEAK_CLOCK_GHZ = 2.4     # GRBM_GUI_ACTIVE is summed over the XCDS dies
 
 
 def clock(path):
