@@ -1060,6 +1060,12 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
         // Steady state of the split forms: every look-ahead load is a whole
         // step, no branch, producers interleaved.  (FP32 matrix instructions
         // do not run alongside vector work, so FP32 takes the plain loop.)
+        // No masks here: every sample these steps stage lies inside the split
+        // (B up to the third-last step, conj(Ey) up to the second-last, both
+        // whole since every step but the last is), and a B column past nx
+        // or a W row past ny, built from the clamped table entries (finite
+        // phases), feeds only its own output column or row, which the
+        // epilogue never stores.
         if constexpr (P::kPresplitA)
         for (; s < nsteps - 3; ++s) {
             const int cur = s & 1;
@@ -1095,20 +1101,15 @@ __global__ __launch_bounds__(kThreads8, 1) void nudft_adj8(const NudftTable tab)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) dreg[j] = q[j];
                 } else if (piece == 2) {          // conj(Ex) of step s+1: first value
-                    const int k = (s + 1) * KC + bk;
-                    const float m0 = (bx_ok && k <= kl) ? P::kBScale : 0.f;
-                    r0 = P::split_b(make_float2(fx0.x * m0, fx0.y * m0));
+                    r0 = P::split_b(cscale(fx0, P::kBScale));
                 } else if (piece == 3) {          // second value; store B(s+1); next phases
-                    const int k = (s + 1) * KC + bk;
-                    const float m1 = (bx_ok && k + 1 <= kl) ? P::kBScale : 0.f;
                     P::template store_b_words<BC>(sB0 + (cur ^ 1) * kBBytes8, bx, bk, r0,
-                                                  P::split_b(make_float2(fx1.x * m1, fx1.y * m1)));
+                                                  P::split_b(cscale(fx1, P::kBScale)));
                     const float2* q = phx + (int64_t)((s + 2) * KC + bk) * nx + xc;
                     fx0 = q[0];
                     fx1 = q[nx];
                 } else if (piece == 4) {          // conj(Ey) of step s+2; fy(s+3)
-                    const float m = (ey_ok && (s + 2) * KC + ek <= kl) ? 1.f : 0.f;
-                    sE[cur][ey][ecol] = make_float2(fy.x * m, fy.y * m);
+                    sE[cur][ey][ecol] = fy;
                     load_fy(s + 3);
                 }
             };
