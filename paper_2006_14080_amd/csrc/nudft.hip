@@ -232,6 +232,54 @@ struct PolSplit {
     // [Br, -Bi] words of one B value; the caller passes the phase already
     // multiplied by kBScale (folded into a mask or a per-thread factor).
     __device__ __forceinline__ static Words split_b(float2 e) { return split2(e.x, -e.y); }
+    // All four B words of one value e = (x, y) converted directly: for the
+    // real output [x, -y] (hi, lo), for the imaginary output [y, x] (hi, lo),
+    // which are the real words with halves swapped and the low half negated
+    // (round to nearest even is symmetric, so the bits equal rot() of the
+    // real words); the sign flips are source modifiers of the packed
+    // conversions.  Fewer vector instructions than split_b plus rot(), but
+    // four words stay live instead of two (used by the forward, whose
+    // producer pieces keep them for one piece only).
+    struct BWords {
+        uint32_t rh, rl, ih, il;
+    };
+    __device__ __forceinline__ static BWords split_b4(float2 e) {
+        const float x = e.x, y = e.y;
+        BWords w;
+        float hx, hy;
+        if constexpr (__is_same(T, __bf16)) {
+            asm("v_cvt_pk_bf16_f32 %0, %1, -%2" : "=v"(w.rh) : "v"(x), "v"(y));
+            asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(w.ih) : "v"(y), "v"(x));
+            hx = __builtin_bit_cast(float, w.ih & 0xffff0000u);
+            hy = __builtin_bit_cast(float, w.ih << 16);
+        } else {
+            asm("v_cvt_pk_f16_f32 %0, %1, -%2" : "=v"(w.rh) : "v"(x), "v"(y));
+            asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(w.ih) : "v"(y), "v"(x));
+            const vec2 h = __builtin_bit_cast(vec2, w.ih);
+            hx = static_cast<float>(h.y);
+            hy = static_cast<float>(h.x);
+        }
+        const float dx = x - hx;
+        const float dyn = hy - y;             // the low part of -y, as (-y) - (-hy)
+        if constexpr (__is_same(T, __bf16)) {
+            asm("v_cvt_pk_bf16_f32 %0, %1, %2" : "=v"(w.rl) : "v"(dx), "v"(dyn));
+            asm("v_cvt_pk_bf16_f32 %0, -%1, %2" : "=v"(w.il) : "v"(dyn), "v"(dx));
+        } else {
+            asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(w.rl) : "v"(dx), "v"(dyn));
+            asm("v_cvt_pk_f16_f32 %0, -%1, %2" : "=v"(w.il) : "v"(dyn), "v"(dx));
+        }
+        return w;
+    }
+    template <int BC>
+    __device__ __forceinline__ static void store_b_words4(char* st, int col, int kp, BWords r0, BWords r1) {
+        const int h = kp >> 2;
+        char* re = st + ((h * 2) * BC + col) * 16 + (kp & 3) * 4;
+        char* im = re + 2 * 2 * BC * 16;
+        *reinterpret_cast<u32x2*>(re) = u32x2{r0.rh, r1.rh};
+        *reinterpret_cast<u32x2*>(re + BC * 16) = u32x2{r0.rl, r1.rl};
+        *reinterpret_cast<u32x2*>(im) = u32x2{r0.ih, r1.ih};
+        *reinterpret_cast<u32x2*>(im + BC * 16) = u32x2{r0.il, r1.il};
+    }
     // B stages hold BC columns: [var][h][part][col], 16 bytes per chunk.
     template <int BC>
     __device__ __forceinline__ static void store_b_words(char* st, int col, int kp, Words r0, Words r1) {
@@ -773,7 +821,7 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
                 QuarterTurn qt;
                 SinCos sc;
                 float2 e0, e1;
-                typename P::Words r0, r1;
+                typename P::BWords r0, r1;
                 auto prod = [&](int piece) {
                     if (piece == 0) {
                         // The next A stage's copies start here, after this
@@ -792,13 +840,13 @@ __global__ __launch_bounds__(kThreads, 2) void nudft_fwd(const NudftTable tab) {
                         e0 = cmul(xb, w0);
                         e1 = cmul(xb, w1);
                     } else if (piece == 3) {
-                        e0 = p_ok ? e0 : make_float2(0.f, 0.f);
-                        e1 = p_ok ? e1 : make_float2(0.f, 0.f);
-                        r0 = P::split_b(e0);
+                        // No sample mask: a column past nk has finite phases
+                        // (frequency 0) and its output is never stored.
+                        r0 = P::split_b4(e0);
                     } else if (piece == 4) {
-                        r1 = P::split_b(e1);
+                        r1 = P::split_b4(e1);
                     } else {
-                        P::template store_b_words<64>(sB0 + (cur ^ 1) * P::kBBytes, pc, pj, r0, r1);
+                        P::template store_b_words4<64>(sB0 + (cur ^ 1) * P::kBBytes, pc, pj, r0, r1);
                     }
                 };
                 P::template mma_with<NT, 64, false>(sA0 + cur * P::kABytes, sB0 + cur * P::kBBytes, wm * (nt * 32),
